@@ -1,0 +1,163 @@
+/*
+ * libdbscan -- DBSCAN on one AMD Instinct MI355X (gfx950), C ABI.
+ *
+ * The library computes the three steps of the paper "Design and optimization
+ * of DBSCAN Algorithm based on CUDA" (Wang et al.):
+ *   step 1  the epsilon test of every ordered pair of points, done on squared
+ *           distances against eps^2 (Section IV-A) and never stored as an
+ *           n x n float matrix (Section IV-B.1 fuses the distance into the
+ *           neighbourhood test);
+ *   step 2  neighbour counts, core flags and primitive clusters (Section IV-B;
+ *           core = "at least MinPts points within eps", Section II);
+ *   step 3  merging of primitive clusters whose centres are reachable core
+ *           points (Section IV-C; reachability as defined in Section II).
+ *
+ * Results are exactly those of the plain float64 definition: for each pair
+ *   s = 0; for k in 0..d-1 { t = x_ik - x_jk; s = s + t*t }  (float64, each
+ *   operation rounded alone), neighbour iff s <= eps*eps (rounded once);
+ * counts include the point itself; core iff count >= minpts; labels are
+ * canonical: a core point's label is the lowest index of a core point in its
+ * cluster, a non-core point with core neighbours takes the label of its
+ * lowest-index core neighbour, every other point is noise (-1).  The kernels
+ * evaluate the distance in float32 (or on BF16/FP16 matrix cores for d >= 16)
+ * only as a filter: every pair whose float32 value lies inside a rigorous
+ * rounding band around eps^2 is re-evaluated in float64 on the GPU, so the
+ * decisions, and therefore counts, core flags and labels, equal the float64
+ * definition bit for bit in every mode.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked DEVICE must be device memory of the current HIP device
+ *     (hipMalloc, or a PyTorch tensor on that device); HOST pointers are
+ *     ordinary host memory.  Point arrays are row-major float32, n rows of d
+ *     coordinates, C-contiguous.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; the call returns once the work is enqueued
+ *     unless a `stats` pointer is given, in which case it waits for the
+ *     stream and fills the statistics.
+ *   - The caller owns every buffer it passes and must keep them alive and
+ *     unmodified until the stream has finished the call's work.
+ *   - Return codes: 0 (DBSCAN_OK) on success; negative DBSCAN_E_* codes on
+ *     failure.  Arguments are checked before anything is enqueued; an
+ *     invalid argument enqueues nothing.  No C++ exception crosses the ABI.
+ *   - Calls are re-entrant on distinct streams.
+ */
+#ifndef DBSCAN_MI355X_H
+#define DBSCAN_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DBSCAN_OK 0
+#define DBSCAN_PENDING 1           /* dbscan_batch_poll: job not finished */
+#define DBSCAN_E_INVAL (-22)       /* bad argument (null pointer, size, eps, minpts) */
+#define DBSCAN_E_NOMEM (-12)       /* device allocation failed / workspace too small */
+#define DBSCAN_E_AGAIN (-11)       /* serving: admission queue full */
+#define DBSCAN_E_DEVICE (-1000)    /* a HIP call failed (hip error in stats) */
+#define DBSCAN_E_NONFINITE (-1001) /* a coordinate is NaN or +-inf */
+#define DBSCAN_E_UNSUPPORTED (-1002)
+
+/* Largest n accepted (indices and labels are int32). */
+#define DBSCAN_MAX_N 2147483583LL
+
+/* How the neighbour relation is kept between step 2 and step 3. */
+#define DBSCAN_ADJ_AUTO 0     /* bitmask when it fits the limit, else on the fly */
+#define DBSCAN_ADJ_BITMASK 1  /* one bit per ordered pair, kept in device memory */
+#define DBSCAN_ADJ_ONTHEFLY 2 /* nothing stored; step 3 repeats the epsilon tests */
+
+/* Arithmetic of the epsilon-test filter (the decision is always float64-exact). */
+#define DBSCAN_PREC_AUTO 0 /* float32 for d < 16, FP16 matrix cores for d >= 16 */
+#define DBSCAN_PREC_FP32 1 /* float32 direct form (x_i - x_j)^2 summed */
+#define DBSCAN_PREC_BF16 2 /* |x|^2 + |y|^2 - 2 x.y on BF16 matrix cores, d >= 16 */
+#define DBSCAN_PREC_FP16 3 /* |x|^2 + |y|^2 - 2 x.y on FP16 matrix cores, d >= 16 */
+
+typedef struct dbscan_opts {
+  int32_t adjacency;          /* DBSCAN_ADJ_*  (0 = auto) */
+  int32_t precision;          /* DBSCAN_PREC_* (0 = auto) */
+  double band_rel;            /* matrix-core filter: re-check every pair with
+                                 |s - eps^2| <= band_rel * eps^2 at least
+                                 (0 = 1e-2); widened to the rigorous bound */
+  uint64_t bitmask_limit;     /* AUTO uses the bitmask when it needs at most this
+                                 many bytes (0 = 16 GiB) */
+  void *workspace;            /* DEVICE, optional: caller-owned scratch of at least
+                                 dbscan_workspace_size() bytes, 256-byte aligned.
+                                 NULL: the library allocates it stream-ordered. */
+  uint64_t workspace_bytes;
+} dbscan_opts;
+
+typedef struct dbscan_stats {
+  int32_t status;         /* DBSCAN_OK, DBSCAN_E_NONFINITE or DBSCAN_E_DEVICE */
+  int32_t hip_error;      /* hipError_t of the failing call, else 0 */
+  int32_t adjacency_used; /* DBSCAN_ADJ_BITMASK or DBSCAN_ADJ_ONTHEFLY */
+  int32_t precision_used; /* DBSCAN_PREC_FP32 / _BF16 / _FP16 */
+  int64_t pairs_tested;   /* ordered pairs of the step-1 sweep (n*n) */
+  int64_t pairs_rechecked;/* pairs of the step-1 sweep re-evaluated in float64 */
+  int64_t core_points;
+  float ms_step1;         /* epsilon tests + counts (+ bitmask), device time */
+  float ms_step2;         /* core flags */
+  float ms_step3;         /* merge, border assignment and labels */
+  float ms_total;         /* whole call, device time */
+  float thr_lo, thr_hi;   /* float32 band thresholds used by the direct form */
+} dbscan_stats;
+
+/*
+ * dbscan_fit -- cluster n points (Sections II and IV: steps 1-3).
+ *   points  DEVICE const float[n*d], row-major, finite values.
+ *   n       1 <= n <= DBSCAN_MAX_N;  1 <= d <= 1024.
+ *   eps     finite, >= 0 (compared as eps*eps rounded once in float64).
+ *   minpts  >= 1 (a point counts itself).
+ *   labels  DEVICE int32[n]  out: -1 noise, else canonical cluster id (a point
+ *           index); filled with -2 when an input coordinate is not finite.
+ *   core    DEVICE uint8[n]  out: 1 for core points, else 0.
+ *   counts  DEVICE int32[n]  out: |N_eps(i)|, the point itself included.
+ *   stream  hipStream_t as void*.
+ * Uses the default options (auto adjacency and precision, library-allocated
+ * workspace).  Asynchronous; a non-finite input is reported through labels
+ * (-2) -- use dbscan_fit_ex with stats to get DBSCAN_E_NONFINITE returned.
+ */
+int dbscan_fit(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+               int32_t *labels, uint8_t *core, int32_t *counts, void *stream);
+
+/*
+ * dbscan_fit_ex -- dbscan_fit with options and statistics.
+ *   opts   HOST, nullable (NULL = defaults).
+ *   stats  HOST, nullable.  When given, the call waits for the stream,
+ *          fills *stats (per-step device times from HIP events on `stream`)
+ *          and returns DBSCAN_E_NONFINITE if an input was not finite.
+ */
+int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+                  int32_t *labels, uint8_t *core, int32_t *counts, void *stream,
+                  const dbscan_opts *opts, dbscan_stats *stats);
+
+/*
+ * dbscan_workspace_size -- bytes of device scratch dbscan_fit_ex needs for
+ * (n, d, opts); *bytes (HOST) receives the size.  The bitmask adjacency needs
+ * ceil(n/256)*256 * ceil(n/256)*256 / 8 bytes; the on-the-fly form needs O(n*d).
+ */
+int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_t *bytes);
+
+/*
+ * dbscan_fp32_band -- the float32 thresholds the direct form uses for eps2
+ * (= eps*eps in float64) and d coordinates: a pair whose float32 squared
+ * distance s32 (any summation order, with or without fused multiply-add)
+ * satisfies s32 <= *lo is a neighbour under the float64 definition, one with
+ * s32 > *hi is not, and pairs in between are re-evaluated in float64.  This
+ * is the rounding-error bound of a sum of d squared differences (Section
+ * IV-B.2 writes the squared distance as that sum).  lo, hi: HOST float*.
+ */
+int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi);
+
+/* dbscan_strerror -- static description of a return code. */
+const char *dbscan_strerror(int code);
+
+/* dbscan_version -- library ABI version (major*10000 + minor*100 + patch). */
+int dbscan_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DBSCAN_MI355X_H */

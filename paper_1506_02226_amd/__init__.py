@@ -1,0 +1,89 @@
+"""DBSCAN on one AMD Instinct MI355X (gfx950).
+
+``fit(points, eps, minpts)`` runs the three steps of Wang et al., "Design and
+optimization of DBSCAN Algorithm based on CUDA" -- the all-pairs epsilon test
+(Section IV-A), neighbour counts, core flags and primitive clusters
+(Section IV-B) and the merge of reachable core points (Section IV-C) -- in the
+HIP kernels of ``libdbscan.so`` behind its C ABI (``include/dbscan.h``).
+PyTorch only provides device memory and the stream.
+
+Outputs equal the float64 definition bit for bit: ``counts`` include the point
+itself, ``core = counts >= minpts``, and ``labels`` are canonical (-1 noise;
+a core point's label is the lowest core index in its cluster; a border point
+takes the label of its lowest-index core neighbour).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+__all__ = ["fit", "workspace_size", "version", "DbscanError"]
+
+DbscanError = _lib.DbscanError
+
+
+def version() -> int:
+    return int(_lib.load().dbscan_version())
+
+
+def workspace_size(n: int, d: int, adjacency: str = "auto", precision: str = "auto",
+                   bitmask_limit: int = 0) -> int:
+    L = _lib.load()
+    opts = _lib.make_opts(adjacency, precision, bitmask_limit=bitmask_limit)
+    out = ctypes.c_uint64(0)
+    rc = L.dbscan_workspace_size(int(n), int(d), ctypes.byref(opts), ctypes.byref(out))
+    if rc != _lib.DBSCAN_OK:
+        raise DbscanError(rc, "dbscan_workspace_size")
+    return int(out.value)
+
+
+def _check_points(points):
+    import torch
+    if not isinstance(points, torch.Tensor):
+        raise TypeError("points must be a torch.Tensor on a ROCm device")
+    if points.device.type != "cuda":
+        raise ValueError("points must live on the GPU (device 'cuda')")
+    if points.dtype != torch.float32 or points.dim() != 2:
+        raise ValueError("points must be a 2-D float32 tensor (n, d)")
+    return points.contiguous()
+
+
+def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: str = "auto",
+        band_rel: float = 0.0, bitmask_limit: int = 0, stats: bool = False, out=None,
+        workspace=None):
+    """Cluster `points` (torch float32 (n, d) on the GPU).
+
+    Returns (labels int32[n], core uint8[n], counts int32[n]) as GPU tensors,
+    plus a statistics dict when ``stats=True`` (the call then waits for the
+    stream).  ``out`` may pass preallocated (labels, core, counts) tensors and
+    ``workspace`` a uint8 GPU tensor of at least ``workspace_size`` bytes."""
+    import torch
+    L = _lib.load()
+    x = _check_points(points)
+    n, d = int(x.shape[0]), int(x.shape[1])
+    dev = x.device
+    if out is None:
+        labels = torch.empty(n, dtype=torch.int32, device=dev)
+        core = torch.empty(n, dtype=torch.uint8, device=dev)
+        counts = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        labels, core, counts = out
+    ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit) if n >= 1 else 0
+    if workspace is None:
+        workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    base = workspace.data_ptr()
+    aligned = (base + 255) // 256 * 256
+    avail = workspace.numel() - (aligned - base)
+    opts = _lib.make_opts(adjacency, precision, band_rel, bitmask_limit, aligned, avail)
+    st = _lib.Stats()
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        rc = L.dbscan_fit_ex(x.data_ptr(), n, d, float(eps), int(minpts), labels.data_ptr(),
+                             core.data_ptr(), counts.data_ptr(), stream, ctypes.byref(opts),
+                             ctypes.byref(st) if stats else None)
+    if rc != _lib.DBSCAN_OK:
+        raise DbscanError(rc, "dbscan_fit_ex")
+    if stats:
+        return labels, core, counts, st.as_dict()
+    return labels, core, counts

@@ -1,0 +1,120 @@
+"""ctypes binding of libdbscan.so (the C ABI declared in include/dbscan.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the shared library.  There is no CPU fallback -- if the library is
+missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdbscan.so")
+
+DBSCAN_OK = 0
+DBSCAN_PENDING = 1
+DBSCAN_E_INVAL = -22
+DBSCAN_E_NOMEM = -12
+DBSCAN_E_AGAIN = -11
+DBSCAN_E_DEVICE = -1000
+DBSCAN_E_NONFINITE = -1001
+DBSCAN_E_UNSUPPORTED = -1002
+
+ADJ = {"auto": 0, "bitmask": 1, "onthefly": 2}
+PREC = {"auto": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+ADJ_NAMES = {v: k for k, v in ADJ.items()}
+PREC_NAMES = {v: k for k, v in PREC.items()}
+
+# Every symbol include/dbscan.h declares.
+EXPORTS = (
+    "dbscan_fit",
+    "dbscan_fit_ex",
+    "dbscan_workspace_size",
+    "dbscan_strerror",
+    "dbscan_version",
+    "dbscan_fp32_band",
+)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [
+        ("adjacency", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("band_rel", ctypes.c_double),
+        ("bitmask_limit", ctypes.c_uint64),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("hip_error", ctypes.c_int32),
+        ("adjacency_used", ctypes.c_int32),
+        ("precision_used", ctypes.c_int32),
+        ("pairs_tested", ctypes.c_int64),
+        ("pairs_rechecked", ctypes.c_int64),
+        ("core_points", ctypes.c_int64),
+        ("ms_step1", ctypes.c_float),
+        ("ms_step2", ctypes.c_float),
+        ("ms_step3", ctypes.c_float),
+        ("ms_total", ctypes.c_float),
+        ("thr_lo", ctypes.c_float),
+        ("thr_hi", ctypes.c_float),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["adjacency_used"] = ADJ_NAMES.get(d["adjacency_used"], d["adjacency_used"])
+        d["precision_used"] = PREC_NAMES.get(d["precision_used"], d["precision_used"])
+        return d
+
+
+class DbscanError(RuntimeError):
+    def __init__(self, code: int, where: str = ""):
+        self.code = code
+        msg = load().dbscan_strerror(code).decode()
+        super().__init__(f"{where}: {msg} ({code})" if where else f"{msg} ({code})")
+
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libdbscan.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"{p} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "or `python paper_1506_02226_amd/build.py`")
+    L = ctypes.CDLL(p)
+    vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    L.dbscan_fit.argtypes = [vp, i64, i32, dbl, i32, vp, vp, vp, vp]
+    L.dbscan_fit.restype = ctypes.c_int
+    L.dbscan_fit_ex.argtypes = [vp, i64, i32, dbl, i32, vp, vp, vp, vp,
+                                ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
+    L.dbscan_fit_ex.restype = ctypes.c_int
+    L.dbscan_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Opts),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+    L.dbscan_workspace_size.restype = ctypes.c_int
+    L.dbscan_strerror.argtypes = [ctypes.c_int]
+    L.dbscan_strerror.restype = ctypes.c_char_p
+    L.dbscan_version.argtypes = []
+    L.dbscan_version.restype = ctypes.c_int
+    L.dbscan_fp32_band.argtypes = [dbl, i32, ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float)]
+    L.dbscan_fp32_band.restype = ctypes.c_int
+    if path is None:
+        _lib = L
+    return L
+
+
+def make_opts(adjacency: str = "auto", precision: str = "auto", band_rel: float = 0.0,
+              bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0) -> Opts:
+    return Opts(ADJ[adjacency], PREC[precision], float(band_rel), int(bitmask_limit),
+                int(workspace) or None, int(workspace_bytes))

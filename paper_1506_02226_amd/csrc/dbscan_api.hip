@@ -1,0 +1,330 @@
+// C ABI of libdbscan (declared in include/dbscan.h): argument checks,
+// workspace layout, float32 band thresholds, kernel sequence.
+#include <errno.h>
+#include <float.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/dbscan.h"
+#include "dbscan_internal.h"
+
+namespace {
+
+constexpr int kVersion = 100;  // 0.1.0
+constexpr int64_t kPadRows = 256;
+constexpr int32_t kMaxD = 1024;
+constexpr uint64_t kDefaultBitmaskLimit = 16ull << 30;
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  int64_t n_pad = 0;
+  int32_t d_pad = 0;
+  int adjacency = DBSCAN_ADJ_ONTHEFLY;
+  int precision = DBSCAN_PREC_FP32;
+  uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
+           off_list = 0, off_adj = 0, total = 0;
+};
+
+uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
+
+int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
+  L->n_pad = round_up(n, kPadRows);
+  const int dc = dbk::coord_chunk(d);
+  L->d_pad = (int32_t)round_up(d, dc);
+  const int req_adj = o ? o->adjacency : DBSCAN_ADJ_AUTO;
+  const int req_prec = o ? o->precision : DBSCAN_PREC_AUTO;
+  const uint64_t limit = (o && o->bitmask_limit) ? o->bitmask_limit : kDefaultBitmaskLimit;
+  if (req_prec == DBSCAN_PREC_AUTO || req_prec == DBSCAN_PREC_FP32)
+    L->precision = DBSCAN_PREC_FP32;
+  else if (req_prec == DBSCAN_PREC_BF16 || req_prec == DBSCAN_PREC_FP16)
+    return DBSCAN_E_UNSUPPORTED;
+  else
+    return DBSCAN_E_INVAL;
+  const bool bm_ok = d <= 4;
+  if (req_adj == DBSCAN_ADJ_BITMASK) {
+    if (!bm_ok) return DBSCAN_E_UNSUPPORTED;
+    L->adjacency = DBSCAN_ADJ_BITMASK;
+  } else if (req_adj == DBSCAN_ADJ_ONTHEFLY) {
+    L->adjacency = DBSCAN_ADJ_ONTHEFLY;
+  } else if (req_adj == DBSCAN_ADJ_AUTO) {
+    L->adjacency =
+        (bm_ok && bitmask_bytes(L->n_pad) <= limit) ? DBSCAN_ADJ_BITMASK : DBSCAN_ADJ_ONTHEFLY;
+  } else {
+    return DBSCAN_E_INVAL;
+  }
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t at = off;
+    off += (uint64_t)round_up((int64_t)bytes, 256);
+    return at;
+  };
+  L->off_state = take(sizeof(dbk::DevState));
+  L->off_soa = take((uint64_t)L->d_pad * L->n_pad * 4);
+  L->off_parent = take((uint64_t)L->n_pad * 4);
+  L->off_jstar = take((uint64_t)L->n_pad * 4);
+  L->off_corebits = take((uint64_t)L->n_pad / 8);
+  L->off_list = take((uint64_t)L->n_pad * 4);
+  L->off_adj = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(bitmask_bytes(L->n_pad)) : off;
+  L->total = off;
+  return DBSCAN_OK;
+}
+
+int check_args(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+               const int32_t *labels, const uint8_t *core, const int32_t *counts) {
+  if (!points || !labels || !core || !counts) return DBSCAN_E_INVAL;
+  if (n < 1 || n > DBSCAN_MAX_N) return DBSCAN_E_INVAL;
+  if (d < 1 || d > kMaxD) return DBSCAN_E_INVAL;
+  if (!(eps >= 0.0) || !isfinite(eps)) return DBSCAN_E_INVAL;
+  if (minpts < 1) return DBSCAN_E_INVAL;
+  return DBSCAN_OK;
+}
+
+// float32 thresholds such that, for the float64 value s64 of the definition
+// and any float32 evaluation s32 of the same sum (any order, with or without
+// fused multiply-add), s32 <= lo implies s64 <= eps2 and s32 > hi implies
+// s64 > eps2.  With u = 2^-24 and u' = 2^-53, a sum of d squared differences
+// evaluated with d+2 roundings per term satisfies |s32 - S| <= g32*S + a and
+// |s64 - S| <= g64*S, S the exact value, g = (d+2)u/(1-(d+2)u); a covers
+// gradual underflow.  The double arithmetic below is widened by 4u' and the
+// results are rounded outward to float32.
+void band_fp32(double eps2, int32_t d, float *lo, float *hi) {
+  if (isinf(eps2)) {
+    *lo = INFINITY;
+    *hi = INFINITY;
+    return;
+  }
+  const double u = 0x1p-24, u64 = 0x1p-53;
+  const double g32 = (d + 2) * u / (1.0 - (d + 2) * u);
+  const double g64 = (d + 2) * u64 / (1.0 - (d + 2) * u64);
+  const double a = (4.0 * d + 4.0) * 0x1p-149;
+  const double lo_d = eps2 * (1.0 - g32) / (1.0 + g64) * (1.0 - 4 * u64) - a;
+  const double hi_d = eps2 * (1.0 + g32) / (1.0 - g64) * (1.0 + 4 * u64) + a;
+  float l = (float)lo_d;
+  if ((double)l > lo_d) l = nextafterf(l, -INFINITY);
+  float h = (float)hi_d;
+  if ((double)h < hi_d) h = nextafterf(h, INFINITY);
+  *lo = l;
+  *hi = h;
+}
+
+struct Chunks {
+  int nchunks;
+  int chunk;  // columns (multiple of 64) or words
+};
+
+// Split `units` column units into chunks so that the grid has enough waves
+// and each chunk's coordinates stay small enough for one XCD's L2.
+Chunks split(int64_t units, int64_t row_waves, int64_t bytes_per_unit, int64_t min_units) {
+  int nch = 1;
+  while (nch < 64 && units / (nch * 2) >= min_units &&
+         (row_waves * nch < 16384 || (units / nch) * bytes_per_unit > (2ll << 20)))
+    nch *= 2;
+  Chunks c;
+  c.chunk = (int)((units + nch - 1) / nch);
+  c.nchunks = (int)((units + c.chunk - 1) / c.chunk);
+  return c;
+}
+
+int hip_fail(hipError_t e, dbscan_stats *stats) {
+  if (stats) {
+    stats->status = DBSCAN_E_DEVICE;
+    stats->hip_error = (int32_t)e;
+  }
+  return DBSCAN_E_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dbscan_version(void) { return kVersion; }
+
+int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi) {
+  if (!lo || !hi || d < 1 || d > kMaxD || !(eps2 >= 0.0)) return DBSCAN_E_INVAL;
+  band_fp32(eps2, d, lo, hi);
+  return DBSCAN_OK;
+}
+
+const char *dbscan_strerror(int code) {
+  switch (code) {
+    case DBSCAN_OK: return "ok";
+    case DBSCAN_PENDING: return "pending";
+    case DBSCAN_E_INVAL: return "invalid argument";
+    case DBSCAN_E_NOMEM: return "out of device memory or workspace too small";
+    case DBSCAN_E_AGAIN: return "admission queue full";
+    case DBSCAN_E_DEVICE: return "HIP runtime error";
+    case DBSCAN_E_NONFINITE: return "input coordinate is NaN or infinite";
+    case DBSCAN_E_UNSUPPORTED: return "unsupported option combination";
+    default: return "unknown error";
+  }
+}
+
+int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_t *bytes) {
+  if (!bytes || n < 1 || n > DBSCAN_MAX_N || d < 1 || d > kMaxD) return DBSCAN_E_INVAL;
+  Layout L;
+  const int rc = plan(n, d, opts, &L);
+  if (rc) return rc;
+  *bytes = L.total;
+  return DBSCAN_OK;
+}
+
+int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+                  int32_t *labels, uint8_t *core, int32_t *counts, void *stream,
+                  const dbscan_opts *opts, dbscan_stats *stats) {
+  int rc = check_args(points, n, d, eps, minpts, labels, core, counts);
+  if (rc) return rc;
+  Layout L;
+  rc = plan(n, d, opts, &L);
+  if (rc) return rc;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  hipStream_t s = (hipStream_t)stream;
+
+  // ---- workspace
+  char *ws = nullptr;
+  bool owned = false;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < L.total) return DBSCAN_E_NOMEM;
+    if (((uintptr_t)opts->workspace & 255u) != 0) return DBSCAN_E_INVAL;
+    ws = (char *)opts->workspace;
+  } else {
+    hipError_t e = hipMallocAsync((void **)&ws, L.total, s);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return (e == hipErrorOutOfMemory) ? DBSCAN_E_NOMEM : hip_fail(e, stats);
+    }
+    owned = true;
+  }
+  auto *st = (dbk::DevState *)(ws + L.off_state);
+  auto *soa = (float *)(ws + L.off_soa);
+  auto *parent = (int *)(ws + L.off_parent);
+  auto *jstar = (int *)(ws + L.off_jstar);
+  auto *corebits = (uint32_t *)(ws + L.off_corebits);
+  auto *list = (int *)(ws + L.off_list);
+  auto *adjT = (uint32_t *)(ws + L.off_adj);
+
+  const double eps2 = eps * eps;
+  float lo, hi;
+  band_fp32(eps2, d, &lo, &hi);
+  const int ni = (int)n, npad = (int)L.n_pad;
+
+  hipEvent_t ev[5] = {};
+  if (stats) {
+    for (auto &e : ev) {
+      hipError_t he = hipEventCreate(&e);
+      if (he != hipSuccess) return hip_fail(he, stats);
+    }
+  }
+  auto mark = [&](int k) {
+    if (stats) (void)hipEventRecord(ev[k], s);
+  };
+
+  hipError_t e = hipSuccess;
+  auto step = [&](hipError_t r) {
+    if (e == hipSuccess && r != hipSuccess) e = r;
+  };
+
+  mark(0);
+  step(dbk::run_reset(st, s));
+  step(dbk::run_stage(points, ni, d, npad, L.d_pad, soa, counts, parent, jstar, st, s));
+
+  dbk::Buffers bufs{};
+  bufs.soa = soa;
+  bufs.counts = counts;
+  bufs.corebits = corebits;
+  bufs.parent = parent;
+  bufs.jstar = jstar;
+  bufs.list = list;
+  bufs.adjT = adjT;
+  bufs.st = st;
+  dbk::SweepScalars sc{};
+  sc.n = ni;
+  sc.n_pad = npad;
+  sc.d = d;
+  sc.d_pad = L.d_pad;
+  sc.lo = lo;
+  sc.hi = hi;
+  sc.eps2 = eps2;
+
+  // ---- step 1 (+ the neighbour counts of step 2)
+  const bool bitmask = L.adjacency == DBSCAN_ADJ_BITMASK;
+  if (bitmask) {
+    const Chunks c = split(npad / 32, npad / 64, 32LL * d * 4, 2);
+    dbk::SweepScalars b1 = sc;
+    b1.nchunks = c.nchunks;
+    b1.chunk = c.chunk;
+    step(dbk::run_bitmask(bufs, b1, s));
+  } else {
+    const int R = dbk::rows_per_wave(d);
+    const Chunks c = split(npad / 64, (n + R - 1) / R, 64LL * L.d_pad * 4, 2);
+    dbk::SweepScalars c1 = sc;
+    c1.nchunks = c.nchunks;
+    c1.chunk = c.chunk * 64;
+    step(dbk::run_count(bufs, c1, s));
+  }
+  mark(1);
+  // ---- step 2: core flags
+  step(dbk::run_core(counts, ni, npad, minpts, core, corebits, st, s));
+  mark(2);
+  // ---- step 3: merge and border assignment
+  if (bitmask) {
+    const Chunks c = split(npad / 32, npad / 64, 1, 8);
+    dbk::SweepScalars b3 = sc;
+    b3.nchunks = c.nchunks;
+    b3.chunk = c.chunk;
+    step(dbk::run_sweep_bitmask(bufs, b3, s));
+  } else {
+    step(dbk::run_union(bufs, sc, s));
+    step(dbk::run_compact_noncore(core, ni, list, st, s));
+    step(dbk::run_border(bufs, sc, s));
+  }
+  step(dbk::run_labels(ni, core, jstar, parent, labels, st, s));
+  mark(3);
+
+  dbk::DevState hst{};
+  if (stats && e == hipSuccess) {
+    step(hipMemcpyAsync(&hst, st, sizeof(hst), hipMemcpyDeviceToHost, s));
+  }
+  if (owned) step(hipFreeAsync(ws, s));
+  if (e != hipSuccess) {
+    if (stats)
+      for (auto &x : ev) (void)hipEventDestroy(x);
+    return hip_fail(e, stats);
+  }
+  if (!stats) return DBSCAN_OK;
+
+  hipError_t se = hipStreamSynchronize(s);
+  if (se != hipSuccess) {
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    return hip_fail(se, stats);
+  }
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
+  (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
+  (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
+  (void)hipEventElapsedTime(&t03, ev[0], ev[3]);
+  for (auto &x : ev) (void)hipEventDestroy(x);
+  stats->adjacency_used = L.adjacency;
+  stats->precision_used = L.precision;
+  stats->pairs_tested = (int64_t)n * (int64_t)n;
+  stats->pairs_rechecked = (int64_t)hst.band_pairs;
+  stats->core_points = (int64_t)hst.core_points;
+  stats->ms_step1 = t01;
+  stats->ms_step2 = t12;
+  stats->ms_step3 = t23;
+  stats->ms_total = t03;
+  stats->thr_lo = lo;
+  stats->thr_hi = hi;
+  stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
+  return stats->status;
+}
+
+int dbscan_fit(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+               int32_t *labels, uint8_t *core, int32_t *counts, void *stream) {
+  return dbscan_fit_ex(points, n, d, eps, minpts, labels, core, counts, stream, nullptr, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,50 @@
+// Host-side launch interface between the C ABI (dbscan_api.hip) and the
+// kernel files.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dbscan_device.h"
+
+namespace dbk {
+
+// Device buffers of one call (all DEVICE pointers).
+struct Buffers {
+  const float *soa;    // [d_pad][n_pad] staged coordinates (NaN-padded columns)
+  int *counts;         // [n]
+  const uint32_t *corebits;  // [n_pad/32]
+  int *parent;         // [n_pad] union-find forest
+  int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
+  const int *list;     // [n_pad] compacted non-core rows
+  uint32_t *adjT;      // [n_pad/32][n_pad] bitmask adjacency (bitmask form only)
+  DevState *st;
+};
+
+// Scalars of one sweep (passed by value; SGPRs in the kernels).
+struct SweepScalars {
+  int n, n_pad, d, d_pad;
+  int nchunks, chunk;  // column split: chunk = columns (multiple of 64) or 32-bit words
+  float lo, hi;        // float32 band: s <= lo in, s > hi out, else float64
+  double eps2;
+};
+
+int rows_per_wave(int d);
+int coord_chunk(int d);
+
+hipError_t run_reset(DevState *st, hipStream_t s);
+hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
+                     int *parent, int *jstar, DevState *st, hipStream_t s);
+hipError_t run_count(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
+                    uint32_t *corebits, DevState *st, hipStream_t s);
+hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
+                               hipStream_t s);
+hipError_t run_sweep_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
+                      const DevState *st, hipStream_t s);
+
+}  // namespace dbk

@@ -1,0 +1,134 @@
+"""The C-ABI library loads, exports every declared symbol, and checks its
+arguments on the host (no device work is started).  CPU only."""
+import ctypes
+import math
+import re
+from fractions import Fraction
+import os
+
+import numpy as np
+import pytest
+
+from paper_1506_02226_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "dbscan.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:int|const char \*)\s*(dbscan_\w+)\s*\(", text, re.M))
+
+
+def test_exports_every_declared_symbol():
+    L = _lib.load()
+    declared = _declared()
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_version_and_strerror():
+    L = _lib.load()
+    assert L.dbscan_version() >= 100
+    assert L.dbscan_strerror(_lib.DBSCAN_E_INVAL) == b"invalid argument"
+    assert L.dbscan_strerror(12345) == b"unknown error"
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n=0), dict(n=-5), dict(d=0), dict(d=1025), dict(eps=-1.0), dict(eps=float("nan")),
+    dict(eps=float("inf")), dict(minpts=0), dict(points=None), dict(labels=None),
+    dict(core=None), dict(counts=None)])
+def test_invalid_arguments_rejected_before_any_device_work(kw):
+    L = _lib.load()
+    args = dict(points=0x1000, n=10, d=2, eps=1.0, minpts=3, labels=0x2000, core=0x3000,
+                counts=0x4000)
+    args.update(kw)
+    rc = L.dbscan_fit_ex(args["points"], args["n"], args["d"], args["eps"], args["minpts"],
+                         args["labels"], args["core"], args["counts"], None, None, None)
+    assert rc == _lib.DBSCAN_E_INVAL
+    rc = L.dbscan_fit(args["points"], args["n"], args["d"], args["eps"], args["minpts"],
+                      args["labels"], args["core"], args["counts"], None)
+    assert rc == _lib.DBSCAN_E_INVAL
+
+
+def test_bad_options_rejected():
+    L = _lib.load()
+    out = ctypes.c_uint64()
+    o = _lib.Opts(7, 0, 0.0, 0, None, 0)
+    assert L.dbscan_workspace_size(100, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+    o = _lib.Opts(1, 0, 0.0, 0, None, 0)  # bitmask needs d <= 4
+    assert L.dbscan_workspace_size(100, 8, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_UNSUPPORTED
+
+
+def test_workspace_size_layout():
+    L = _lib.load()
+    out = ctypes.c_uint64()
+    bm = _lib.make_opts("bitmask")
+    assert L.dbscan_workspace_size(200_000, 2, ctypes.byref(bm), ctypes.byref(out)) == 0
+    n_pad = 200_192
+    assert out.value >= n_pad * n_pad // 8
+    fly = _lib.make_opts("onthefly")
+    assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(fly), ctypes.byref(out)) == 0
+    assert out.value < 64 * 2_000_128  # O(n d)
+    auto = _lib.make_opts("auto")
+    assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(auto), ctypes.byref(out)) == 0
+    assert out.value < 64 * 2_000_128  # auto picks on-the-fly: bitmask would be 500 GB
+
+
+def _band(eps2, d):
+    L = _lib.load()
+    lo, hi = ctypes.c_float(), ctypes.c_float()
+    assert L.dbscan_fp32_band(eps2, d, ctypes.byref(lo), ctypes.byref(hi)) == 0
+    return lo.value, hi.value
+
+
+def test_band_is_narrow_and_brackets_eps2():
+    for eps in (0.25, 0.3, 0.4, 1.0, 6.0, 1e-3):
+        eps2 = eps * eps
+        for d in (1, 2, 3, 4, 16, 64):
+            lo, hi = _band(eps2, d)
+            assert lo < eps2 < hi
+            # 2(d+2) roundings of relative size 2^-24 plus one float32 ulp on each side
+            assert (hi - lo) / eps2 < (2 * (d + 2) + 8) * 2.0 ** -24
+
+
+def test_band_edge_values():
+    lo, hi = _band(0.0, 2)
+    assert lo < 0.0 < hi < 1e-40
+    lo, hi = _band(float("inf"), 2)
+    assert math.isinf(lo) and math.isinf(hi)
+    lo, hi = _band(1e39, 3)  # above float32 range
+    assert math.isinf(hi) and lo == np.finfo(np.float32).max
+
+
+def test_band_sound_on_adversarial_pairs():
+    """Pairs placed within a few float32 ulps of eps: whenever the float32
+    direct form (emulated in numpy float32, both with and without a fused
+    last step) says "in" by the lower threshold or "out" by the upper one,
+    exact rational arithmetic agrees."""
+    rng = np.random.default_rng(1)
+    checked = 0
+    for _ in range(3000):
+        d = int(rng.integers(1, 5))
+        eps = float(rng.choice([0.25, 0.3, 0.4, 1.0]))
+        eps2 = eps * eps
+        lo, hi = _band(eps2, d)
+        a = rng.uniform(0, 500, size=d).astype(np.float32)
+        v = rng.standard_normal(d)
+        v /= np.linalg.norm(v)
+        b = (a.astype(np.float64) + eps * v).astype(np.float32)
+        b[0] = b[0] + np.float32(rng.integers(-3, 4)) * np.spacing(b[0])
+        t = (a - b).astype(np.float32)
+        s32 = np.float32(0)
+        for k in range(d):
+            s32 = np.float32(s32 + np.float32(t[k] * t[k]))
+        exact = sum((Fraction(float(x)) - Fraction(float(y))) ** 2 for x, y in zip(a, b))
+        e2 = Fraction(eps2)
+        if s32 <= lo:
+            assert exact <= e2 * (1 + Fraction(1, 2 ** 50))
+            checked += 1
+        if s32 > hi:
+            assert exact > e2 * (1 - Fraction(1, 2 ** 50))
+            checked += 1
+    assert checked > 1000

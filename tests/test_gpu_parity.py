@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Counts, core flags and labels must be bit-identical to the float64 oracle.
+Sizes stay where the oracle finishes in seconds but span several tiles and
+ragged tails; full-size workloads are checked on sampled rows (exact) and on
+invariants that hold at any size."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1506_02226_amd as pkg
+from oracle import c_oracle, dbscan_oracle as orc
+from paper_1506_02226_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+MODES = ("bitmask", "onthefly")
+
+
+def _gpu(points):
+    return torch.from_numpy(np.ascontiguousarray(points, dtype=np.float32)).to("cuda:0")
+
+
+def run(points, eps, minpts, **kw):
+    out = pkg.fit(_gpu(points), eps, minpts, **kw)
+    torch.cuda.synchronize()
+    res = [t.cpu().numpy() for t in out[:3]]
+    res[1] = res[1].astype(bool)
+    if kw.get("stats"):
+        return (*res, out[3])
+    return tuple(res)
+
+
+def assert_same(gpu, ref, what=""):
+    lab, core, cnt = gpu[:3]
+    rl, rc, rn = ref
+    np.testing.assert_array_equal(cnt, np.asarray(rn), err_msg=f"counts {what}")
+    np.testing.assert_array_equal(core, np.asarray(rc).astype(bool), err_msg=f"core {what}")
+    np.testing.assert_array_equal(lab, np.asarray(rl), err_msg=f"labels {what}")
+
+
+def modes_for(d):
+    return MODES if d <= 4 else ("onthefly",)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_handworked_fixture(handworked, mode):
+    pts, eps, minpts, counts, core, labels = handworked
+    assert_same(run(pts, eps, minpts, adjacency=mode), (labels, core, counts), mode)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_blobs2d_small(mode):
+    w = wl.blobs2d_small(0)
+    gpu = run(w.points, w.eps, w.minpts, adjacency=mode, stats=True)
+    assert_same(gpu, orc.dbscan(w.points, w.eps, w.minpts), mode)
+    st = gpu[3]
+    assert st["adjacency_used"] == mode and st["pairs_tested"] == w.n * w.n
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4099])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 16, 64])
+def test_ragged_random(n, d):
+    rng = np.random.default_rng(1000 * n + d)
+    k = max(1, n // 50)
+    centres = rng.uniform(0, 10, size=(k, d))
+    pts = (centres[rng.integers(0, k, size=n)] + 0.3 * rng.standard_normal((n, d))).astype(np.float32)
+    eps = float(0.35 * np.sqrt(d))
+    minpts = int(rng.integers(1, 8))
+    ref = orc.dbscan(pts, eps, minpts)
+    for mode in modes_for(d):
+        assert_same(run(pts, eps, minpts, adjacency=mode), ref, f"n={n} d={d} {mode}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_integer_grid_ties(mode):
+    """Every neighbour pair of a unit grid sits exactly at eps: all of them
+    fall in the float32 band and are decided in float64."""
+    g = np.stack(np.meshgrid(np.arange(40), np.arange(30)), -1).reshape(-1, 2).astype(np.float32)
+    rng = np.random.default_rng(5)
+    g = g[rng.permutation(len(g))]
+    g = np.concatenate([g, g[:100]])  # duplicates
+    for eps, minpts in ((1.0, 5), (1.0, 6), (np.sqrt(2.0), 9), (2.0, 13)):
+        gpu = run(g, eps, minpts, adjacency=mode, stats=True)
+        assert_same(gpu, orc.dbscan(g, eps, minpts), f"eps={eps} minpts={minpts}")
+        if eps == 1.0:
+            assert gpu[3]["pairs_rechecked"] > 0
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_cases(mode):
+    rng = np.random.default_rng(9)
+    pts = rng.uniform(0, 5, size=(300, 2)).astype(np.float32)
+    same = np.zeros((200, 3), np.float32) + 1.5
+    for p, eps, minpts in ((pts, 0.0, 1), (pts, 0.0, 2), (pts, 100.0, 300), (pts, 100.0, 301),
+                           (pts, 0.4, 1), (same, 0.0, 200), (same, 0.0, 201),
+                           (np.float32([[3.0, 4.0]]), 1.0, 1), (np.float32([[3.0, 4.0]]), 1.0, 2)):
+        if p.shape[1] > 4 and mode == "bitmask":
+            continue
+        assert_same(run(p, eps, minpts, adjacency=mode), orc.dbscan(p, eps, minpts),
+                    f"eps={eps} minpts={minpts} n={len(p)}")
+
+
+def test_large_coordinates_and_tiny_eps():
+    rng = np.random.default_rng(12)
+    base = rng.uniform(-1e6, 1e6, size=(50, 3))
+    pts = (base[rng.integers(0, 50, 600)] + rng.standard_normal((600, 3)) * 0.05).astype(np.float32)
+    for eps, minpts in ((0.1, 3), (1e-3, 2), (0.0625, 4)):
+        ref = orc.dbscan(pts, eps, minpts)
+        for mode in MODES:
+            assert_same(run(pts, eps, minpts, adjacency=mode), ref, f"eps={eps} {mode}")
+
+
+def test_nonfinite_input_reported():
+    pts = np.random.default_rng(0).uniform(0, 1, size=(100, 2)).astype(np.float32)
+    pts[17, 1] = np.nan
+    with pytest.raises(pkg.DbscanError) as ei:
+        pkg.fit(_gpu(pts), 0.1, 3, stats=True)
+    assert ei.value.code == pkg._lib.DBSCAN_E_NONFINITE
+    labels, core, counts = pkg.fit(_gpu(pts), 0.1, 3)
+    torch.cuda.synchronize()
+    assert (labels.cpu().numpy() == -2).all()
+
+
+def test_invalid_arguments_raise():
+    x = _gpu(np.zeros((10, 2), np.float32))
+    with pytest.raises(pkg.DbscanError):
+        pkg.fit(x, -1.0, 3)
+    with pytest.raises(pkg.DbscanError):
+        pkg.fit(x, 1.0, 0)
+    with pytest.raises(pkg.DbscanError):
+        pkg.fit(_gpu(np.zeros((10, 8), np.float32)), 1.0, 3, adjacency="bitmask")
+
+
+def test_library_allocated_workspace_and_side_stream():
+    """dbscan_fit (library-owned, stream-ordered workspace) on a side stream."""
+    w = wl.blobs2d_small(3)
+    L = pkg._lib.load()
+    x = _gpu(w.points)
+    n = w.n
+    labels = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    core = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    rc = L.dbscan_fit(x.data_ptr(), n, 2, w.eps, w.minpts, labels.data_ptr(), core.data_ptr(),
+                      counts.data_ptr(), s.cuda_stream)
+    assert rc == 0
+    s.synchronize()
+    assert_same((labels.cpu().numpy(), core.cpu().numpy().astype(bool), counts.cpu().numpy()),
+                orc.dbscan(w.points, w.eps, w.minpts))
+
+
+def test_repeatable():
+    w = wl.blobs2d_200k(0, n=20_000)
+    a = run(w.points, w.eps, w.minpts, adjacency="bitmask")
+    b = run(w.points, w.eps, w.minpts, adjacency="bitmask")
+    c = run(w.points, w.eps, w.minpts, adjacency="onthefly")
+    for x, y, z in zip(a, b, c):
+        np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(x, z)
+
+
+@pytest.mark.parametrize("name,n", [("blobs2d_200k", 30_000), ("aniso3d_2m", 30_000),
+                                    ("mix64d_300k_q50", 6_000)])
+def test_scaled_recipes_full_parity(name, n):
+    """Each workload recipe at a size the C oracle finishes in seconds."""
+    w = wl.by_name(name, 0, n)
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    for mode in modes_for(w.d):
+        assert_same(run(w.points, w.eps, w.minpts, adjacency=mode), ref, f"{name} {mode}")
+
+
+def _sampled_checks(w, gpu, rows):
+    """Exact per-row checks against the oracle at any size."""
+    lab, core, cnt = gpu[:3]
+    n = w.n
+    assert (core == (cnt >= w.minpts)).all()
+    ref_cnt = c_oracle.row_counts(w.points, w.eps, rows)
+    np.testing.assert_array_equal(cnt[rows], ref_cnt)
+    # canonical labels everywhere
+    nz = lab >= 0
+    assert (lab >= -1).all()
+    assert core[lab[nz]].all()
+    assert (lab[lab[nz]] == lab[nz]).all()
+    ci = np.flatnonzero(core)
+    assert (lab[ci] <= ci).all() and (lab[ci] >= 0).all()
+    # per sampled row: neighbours, their exact core flags, label rules
+    for i in rows[:4]:
+        nb = np.flatnonzero(c_oracle.row_neighbours(w.points, w.eps, int(i)))
+        nb_core = c_oracle.row_counts(w.points, w.eps, nb) >= w.minpts
+        np.testing.assert_array_equal(core[nb], nb_core)
+        core_nb = nb[nb_core]
+        if core[i]:
+            assert (lab[core_nb] == lab[i]).all()
+        elif core_nb.size:
+            assert lab[i] == lab[core_nb.min()]
+        else:
+            assert lab[i] == -1
+    assert n == len(lab)
+
+
+def test_blobs2d_200k_full_size():
+    w = wl.blobs2d_200k(0)
+    gpu = run(w.points, w.eps, w.minpts, stats=True)
+    assert gpu[3]["adjacency_used"] == "bitmask"
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(w.n, 64, replace=False))
+    rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:8]])
+    _sampled_checks(w, gpu, rows)
+    other = run(w.points, w.eps, w.minpts, adjacency="onthefly")
+    for x, y in zip(gpu[:3], other):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_aniso3d_2m_full_size():
+    w = wl.aniso3d_2m(0)
+    gpu = run(w.points, w.eps, w.minpts, stats=True)
+    assert gpu[3]["adjacency_used"] == "onthefly"
+    rng = np.random.default_rng(1)
+    rows = np.sort(rng.choice(w.n, 16, replace=False))
+    rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]])
+    _sampled_checks(w, gpu, rows)
