@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""DBSCAN throughput on one MI355X.
+
+One step = one full ``dbscan_fit`` (steps 1-3 of the paper: all-pairs epsilon
+test with neighbour counts and bitmask, core flags, union-find merge, border
+assignment, labels) on device-resident synthetic points.  Default workload:
+200,000 2-D points, 50 Gaussian blobs + 5% noise, eps=0.25, MinPts=10,
+bitmask adjacency.
+
+Prints one JSON line: whole-job epsilon-pair tests per second (n^2 per step),
+points clustered per second, the dominant kernel's roofline fraction (timed
+with HIP events recorded by the library on the launch stream) and the CPU
+oracle timed on a bounded sample on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes, one wave64 VALU instruction per SIMD
+# every 4 cycles at 2.4 GHz -> 39.32e12 VALU lane-operations per second.
+VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+HBM_PEAK_BYTES = 8.0e12
+
+
+def valu_ops_per_pair(d: int) -> int:
+    """Minimum VALU lane-operations of the float32 direct form per ordered
+    pair without packed math: d subtractions, 1 multiply, d-1 fused
+    multiply-adds and 1 compare."""
+    return 2 * d + 1
+
+
+class HipEvents:
+    def __init__(self):
+        self.lib = ctypes.CDLL("libamdhip64.so")
+        self.lib.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.lib.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p,
+                                                 ctypes.c_void_p]
+        self.lib.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def block(self, k: int):
+        arr = (ctypes.c_void_p * k)()
+        for i in range(k):
+            e = ctypes.c_void_p()
+            rc = self.lib.hipEventCreate(ctypes.byref(e))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed: {rc}")
+            arr[i] = e.value
+        return arr
+
+    def elapsed(self, a, b) -> float:
+        ms = ctypes.c_float()
+        rc = self.lib.hipEventElapsedTime(ctypes.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(ms.value)
+
+    def destroy(self, arr):
+        for e in arr:
+            self.lib.hipEventDestroy(e)
+
+
+def cpu_baseline(w, sample_n: int):
+    from oracle import c_oracle
+    m = min(sample_n, w.n)
+    pts = np.ascontiguousarray(w.points[:m])
+    threads = c_oracle.threads(0)
+    t0 = time.perf_counter()
+    c_oracle.dbscan(pts, w.eps, w.minpts, threads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(m * m / dt / 1e9, 4),
+        "unit": "Gpairs/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"full C oracle (float64 counts, BFS, border) on the first {m} points of the "
+                   f"shuffled workload (a uniform random subsample), {dt:.1f} s; rate = m^2/t"),
+    }
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="blobs2d_200k")
+    ap.add_argument("--adjacency", default="auto", choices=["auto", "bitmask", "onthefly"])
+    ap.add_argument("--cpu-sample", type=int, default=80_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); rows shard across GPUs only in the design notes.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_1506_02226_amd as pkg
+    from paper_1506_02226_amd import workloads
+
+    w = workloads.by_name(args.workload)
+    n, d = w.n, w.d
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(w.points).to(dev)
+    labels = torch.empty(n, dtype=torch.int32, device=dev)
+    core = torch.empty(n, dtype=torch.uint8, device=dev)
+    counts = torch.empty(n, dtype=torch.int32, device=dev)
+    ws_bytes = pkg.workspace_size(n, d, args.adjacency)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    out = (labels, core, counts)
+
+    # one checked call first: statistics (adjacency used, band pairs)
+    _, _, _, st = pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, stats=True, out=out,
+                          workspace=ws)
+
+    hip = HipEvents()
+    ev = [hip.block(4) for _ in range(args.steps)]
+    for _ in range(args.warmup):
+        pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, out=out, workspace=ws,
+                events=ctypes.addressof(ev[k]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) / args.steps * 1e3
+    s1 = [hip.elapsed(e[0], e[1]) for e in ev]
+    s2 = [hip.elapsed(e[1], e[2]) for e in ev]
+    s3 = [hip.elapsed(e[2], e[3]) for e in ev]
+    for e in ev:
+        hip.destroy(e)
+
+    pairs = float(n) * float(n)
+    k_ms = float(np.mean(s1))
+    achieved = pairs * valu_ops_per_pair(d) / (k_ms * 1e-3) / 1e12
+    peak = VALU_LANE_OPS_PEAK / 1e12
+    kernel = "k_bitmask" if st["adjacency_used"] == "bitmask" else "k_count_small"
+    rec = {
+        "metric": "eps-pair tests/sec (Gpairs/s) + points clustered/s",
+        "value": round(pairs / (ms_step * 1e-3) / 1e9, 3),
+        "unit": "Gpairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "d": d, "eps": w.eps, "minpts": w.minpts,
+                   "seed": w.meta.get("seed", 0), "adjacency": st["adjacency_used"],
+                   "precision": st["precision_used"]},
+        "points_per_s": round(n / (ms_step * 1e-3), 1),
+        "step1_gpairs_per_s": round(pairs / (k_ms * 1e-3) / 1e9, 3),
+        "phase_ms": {"step1": round(k_ms, 4), "step2": round(float(np.mean(s2)), 4),
+                     "step3": round(float(np.mean(s3)), 4)},
+        "pairs_rechecked_fp64": int(st["pairs_rechecked"]),
+        "core_points": int(st["core_points"]),
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
+                     "peak": round(peak, 3), "unit": "Tlane-op/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "ops_per_pair": valu_ops_per_pair(d)},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -86,6 +86,10 @@ typedef struct dbscan_opts {
                                  dbscan_workspace_size() bytes, 256-byte aligned.
                                  NULL: the library allocates it stream-ordered. */
   uint64_t workspace_bytes;
+  void *events;               /* HOST, optional: hipEvent_t[4] created by the caller.
+                                 Recorded on `stream` (no wait) before the step-1
+                                 kernel and after steps 1, 2 and 3, so the caller
+                                 can time the kernels of a call it does not wait for. */
 } dbscan_opts;
 
 typedef struct dbscan_stats {
@@ -99,7 +103,7 @@ typedef struct dbscan_stats {
   float ms_step1;         /* epsilon tests + counts (+ bitmask), device time */
   float ms_step2;         /* core flags */
   float ms_step3;         /* merge, border assignment and labels */
-  float ms_total;         /* whole call, device time */
+  float ms_total;         /* steps 1-3, device time (input staging excluded) */
   float thr_lo, thr_hi;   /* float32 band thresholds used by the direct form */
 } dbscan_stats;
 

@@ -51,13 +51,15 @@ def _check_points(points):
 
 def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: str = "auto",
         band_rel: float = 0.0, bitmask_limit: int = 0, stats: bool = False, out=None,
-        workspace=None):
+        workspace=None, events: int = 0):
     """Cluster `points` (torch float32 (n, d) on the GPU).
 
     Returns (labels int32[n], core uint8[n], counts int32[n]) as GPU tensors,
     plus a statistics dict when ``stats=True`` (the call then waits for the
     stream).  ``out`` may pass preallocated (labels, core, counts) tensors and
-    ``workspace`` a uint8 GPU tensor of at least ``workspace_size`` bytes."""
+    ``workspace`` a uint8 GPU tensor of at least ``workspace_size`` bytes.
+    ``events`` is the address of a caller-created hipEvent_t[4] that the
+    library records around the steps (see dbscan_opts.events)."""
     import torch
     L = _lib.load()
     x = _check_points(points)
@@ -75,7 +77,7 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
     base = workspace.data_ptr()
     aligned = (base + 255) // 256 * 256
     avail = workspace.numel() - (aligned - base)
-    opts = _lib.make_opts(adjacency, precision, band_rel, bitmask_limit, aligned, avail)
+    opts = _lib.make_opts(adjacency, precision, band_rel, bitmask_limit, aligned, avail, events)
     st = _lib.Stats()
     stream = torch.cuda.current_stream(dev).cuda_stream
     with torch.cuda.device(dev):

@@ -45,6 +45,7 @@ class Opts(ctypes.Structure):
         ("bitmask_limit", ctypes.c_uint64),
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
+        ("events", ctypes.c_void_p),
     ]
 
 
@@ -115,6 +116,7 @@ def load(path: str | None = None):
 
 
 def make_opts(adjacency: str = "auto", precision: str = "auto", band_rel: float = 0.0,
-              bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0) -> Opts:
+              bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0,
+              events: int = 0) -> Opts:
     return Opts(ADJ[adjacency], PREC[precision], float(band_rel), int(bitmask_limit),
-                int(workspace) or None, int(workspace_bytes))
+                int(workspace) or None, int(workspace_bytes), int(events) or None)

@@ -218,8 +218,10 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
       if (he != hipSuccess) return hip_fail(he, stats);
     }
   }
+  hipEvent_t *user_ev = (opts && opts->events) ? (hipEvent_t *)opts->events : nullptr;
   auto mark = [&](int k) {
     if (stats) (void)hipEventRecord(ev[k], s);
+    if (user_ev) (void)hipEventRecord(user_ev[k], s);
   };
 
   hipError_t e = hipSuccess;
@@ -227,9 +229,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
 
-  mark(0);
   step(dbk::run_reset(st, s));
   step(dbk::run_stage(points, ni, d, npad, L.d_pad, soa, counts, parent, jstar, st, s));
+  mark(0);
 
   dbk::Buffers bufs{};
   bufs.soa = soa;
