@@ -27,9 +27,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes, one wave64 VALU instruction per SIMD
-# every 4 cycles at 2.4 GHz -> 39.32e12 VALU lane-operations per second.
-VALU_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
+# MI355X ALU peak in VALU lane-operations per second: 256 CUs at 2.4 GHz
+# issuing up to two wave64 VALU instructions per clock per CU (128 lanes),
+# the published 157.3 TFLOP/s FP32 vector rate counted as FMA lanes.  A
+# probe measured 1.83 wave-instructions/clock/CU for independent v_mul_f32,
+# so the one-per-SIMD-every-4-clocks figure (39.3e12) is not a ceiling.
+VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
 
 

@@ -86,6 +86,11 @@ typedef struct dbscan_opts {
                                  dbscan_workspace_size() bytes, 256-byte aligned.
                                  NULL: the library allocates it stream-ordered. */
   uint64_t workspace_bytes;
+  uint64_t pair_capacity;     /* on-the-fly form, d <= 4: room for this many
+                                 neighbour pairs (i, j), j < i, recorded by step 1
+                                 for the merge (8 bytes each; 0 = 128 per point).
+                                 If they do not fit, step 3 repeats the epsilon
+                                 tests instead; results are identical. */
   void *events;               /* HOST, optional: hipEvent_t[4] created by the caller.
                                  Recorded on `stream` (no wait) before the step-1
                                  kernel and after steps 1, 2 and 3, so the caller
@@ -98,13 +103,17 @@ typedef struct dbscan_stats {
   int32_t adjacency_used; /* DBSCAN_ADJ_BITMASK or DBSCAN_ADJ_ONTHEFLY */
   int32_t precision_used; /* DBSCAN_PREC_FP32 / _BF16 / _FP16 */
   int64_t pairs_tested;   /* ordered pairs of the step-1 sweep (n*n) */
-  int64_t pairs_rechecked;/* pairs of the step-1 sweep re-evaluated in float64 */
+  int64_t pairs_rechecked;/* pair tests re-evaluated in float64 (all steps) */
   int64_t core_points;
   float ms_step1;         /* epsilon tests + counts (+ bitmask), device time */
   float ms_step2;         /* core flags */
   float ms_step3;         /* merge, border assignment and labels */
   float ms_total;         /* steps 1-3, device time (input staging excluded) */
   float thr_lo, thr_hi;   /* float32 band thresholds used by the direct form */
+  int64_t pairs_listed;   /* neighbour pairs j < i found by step 1 (pair list) */
+  int32_t pair_overflow;  /* 1 if they exceeded pair_capacity (step 3 repeated
+                             the tests), else 0 */
+  int32_t reserved;
 } dbscan_stats;
 
 /*

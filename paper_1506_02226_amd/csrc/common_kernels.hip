@@ -1,0 +1,171 @@
+// Kernels shared by both forms: staging (the transposed coordinate layout of
+// Section IV-A.2), core flags (Section II, definition 2; the `valid` vector of
+// Section IV-B), compaction of non-core rows, the merge and border pass over
+// the neighbour-pair list, and canonical labels.
+#include "dbscan_device.h"
+#include "dbscan_internal.h"
+
+namespace dbk {
+
+// ------------------------------------------------------------------ staging
+__global__ void k_reset_state(DevState *st) {
+  if (threadIdx.x == 0) {
+    st->status = 0;
+    st->noncore = 0;
+    st->band_pairs = 0;
+    st->core_points = 0;
+    st->edges = 0;
+  }
+}
+
+// soa[k][i] = points[i][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n.
+// Also clears counts, parent = identity, jstar = none; flags non-finite input.
+__global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, int d_pad,
+                        float *__restrict__ soa, int *__restrict__ counts,
+                        int *__restrict__ parent, int *__restrict__ jstar, DevState *st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;
+  bool bad = false;
+  const float qnan = __builtin_nanf("");
+  for (int k = 0; k < d_pad; ++k) {
+    float v;
+    if (i < n) {
+      v = (k < d) ? pts[(size_t)i * d + k] : 0.0f;
+      bad |= !__builtin_isfinite(v);
+    } else {
+      v = qnan;
+    }
+    soa[(size_t)k * n_pad + i] = v;
+  }
+  if (i < n) {
+    counts[i] = 0;
+    parent[i] = i;
+    jstar[i] = kNoNeighbour;
+  }
+  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNonFinite);
+}
+
+// ------------------------------------------------------------- core flags
+__global__ void k_core(const int *__restrict__ counts, int n, int n_pad, int minpts,
+                       uint8_t *__restrict__ core, uint32_t *__restrict__ corebits,
+                       DevState *st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_pad) return;  // n_pad is a multiple of 64: whole waves
+  const bool c = i < n && counts[i] >= minpts;
+  if (i < n) core[i] = c ? 1 : 0;
+  const uint64_t m = __ballot(c);
+  const int lane = lane_id();
+  if (lane == 0) {
+    corebits[i >> 5] = (uint32_t)m;
+    corebits[(i >> 5) + 1] = (uint32_t)(m >> 32);
+    if (m) atomicAdd(&st->core_points, (unsigned long long)__popcll(m));
+  }
+}
+
+// Non-core rows into a list (any order) for the border pass that repeats the
+// epsilon tests.  With `only_on_overflow` it runs only when the pair list
+// overflowed (otherwise the pair list serves the border points).
+__global__ void k_compact_noncore(const uint8_t *__restrict__ core, int n, int *__restrict__ list,
+                                  DevState *st, int only_on_overflow) {
+  if (only_on_overflow && !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT) & kStatusEdgeOverflow))
+    return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool nc = i < n && core[i] == 0;
+  const uint64_t m = __ballot(nc);
+  if (m == 0ull) return;
+  const int lane = lane_id();
+  int base = 0;
+  if (lane == 0) base = (int)atomicAdd(&st->noncore, (unsigned)__popcll(m));
+  base = __shfl(base, 0);
+  if (nc) list[base + __popcll(m & ((1ull << lane) - 1ull))] = i;
+}
+
+// --------------------------------------------- merge + border from the list
+// Every neighbour pair (a, b), b < a, found by step 1: core-core pairs are
+// joined in the union-find; a non-core end takes the smaller index of its
+// core neighbours (atomicMin), which after all pairs is its lowest-index core
+// neighbour.  Skipped when the list overflowed.
+__global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pairs,
+                                                    const uint32_t *__restrict__ corebits,
+                                                    int *__restrict__ parent,
+                                                    int *__restrict__ jstar, DevState *st,
+                                                    long long cap) {
+  const unsigned status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (status & kStatusEdgeOverflow) return;
+  unsigned long long total =
+      __hip_atomic_load(&st->edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (total > (unsigned long long)cap) total = (unsigned long long)cap;
+  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+  for (unsigned long long e = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+       e < total; e += stride) {
+    const int2 pr = pairs[e];
+    const bool ca = (corebits[pr.x >> 5] >> (pr.x & 31)) & 1u;
+    const bool cb = (corebits[pr.y >> 5] >> (pr.y & 31)) & 1u;
+    if (ca && cb)
+      uf_union(parent, pr.x, pr.y);
+    else if (ca)
+      atomicMin(jstar + pr.y, pr.x);
+    else if (cb)
+      atomicMin(jstar + pr.x, pr.y);
+  }
+}
+
+// ------------------------------------------------------------------ labels
+__global__ void k_labels(int n, const uint8_t *__restrict__ core, const int *__restrict__ jstar,
+                         int *__restrict__ parent, int *__restrict__ labels, const DevState *st) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (st->status & kStatusNonFinite) {
+    labels[i] = -2;
+    return;
+  }
+  if (core[i]) {
+    labels[i] = uf_find(parent, i);
+  } else {
+    const int j = jstar[i];
+    labels[i] = (j == kNoNeighbour) ? -1 : uf_find(parent, j);
+  }
+}
+
+// ------------------------------------------------------------ host launchers
+hipError_t run_reset(DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
+                     int *parent, int *jstar, DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, n, d, n_pad, d_pad,
+                     soa, counts, parent, jstar, st);
+  return hipGetLastError();
+}
+
+hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
+                    uint32_t *corebits, DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_core, dim3((n_pad + 255) / 256), dim3(256), 0, s, counts, n, n_pad, minpts,
+                     core, corebits, st);
+  return hipGetLastError();
+}
+
+hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
+                               bool only_on_overflow, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_noncore, dim3((n + 255) / 256), dim3(256), 0, s, core, n, list, st,
+                     only_on_overflow ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_merge_list, dim3(2048), dim3(256), 0, s, b.pairs, b.corebits, b.parent,
+                     b.jstar, b.st, cap);
+  return hipGetLastError();
+}
+
+hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
+                      const DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_labels, dim3((n + 255) / 256), dim3(256), 0, s, n, core, jstar, parent,
+                     labels, st);
+  return hipGetLastError();
+}
+
+}  // namespace dbk

@@ -17,6 +17,8 @@ constexpr int kVersion = 100;  // 0.1.0
 constexpr int64_t kPadRows = 256;
 constexpr int32_t kMaxD = 1024;
 constexpr uint64_t kDefaultBitmaskLimit = 16ull << 30;
+constexpr uint64_t kPairsPerPoint = 128;       // default pair-list capacity per point
+constexpr uint64_t kMaxPairs = 2147483647ull;  // 16 GiB of (int, int) pairs
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -26,7 +28,8 @@ struct Layout {
   int adjacency = DBSCAN_ADJ_ONTHEFLY;
   int precision = DBSCAN_PREC_FP32;
   uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
-           off_list = 0, off_adj = 0, total = 0;
+           off_list = 0, off_adj = 0, off_pairs = 0, total = 0;
+  int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4)
 };
 
 uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
@@ -69,6 +72,11 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->off_corebits = take((uint64_t)L->n_pad / 8);
   L->off_list = take((uint64_t)L->n_pad * 4);
   L->off_adj = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(bitmask_bytes(L->n_pad)) : off;
+  if (L->adjacency == DBSCAN_ADJ_ONTHEFLY && d <= 4) {
+    const uint64_t req = (o && o->pair_capacity) ? o->pair_capacity : (uint64_t)kPairsPerPoint * n;
+    L->edge_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
+  }
+  L->off_pairs = L->edge_cap ? take((uint64_t)L->edge_cap * 8) : off;
   L->total = off;
   return DBSCAN_OK;
 }
@@ -205,6 +213,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   auto *corebits = (uint32_t *)(ws + L.off_corebits);
   auto *list = (int *)(ws + L.off_list);
   auto *adjT = (uint32_t *)(ws + L.off_adj);
+  auto *pairs = (int2 *)(ws + L.off_pairs);
 
   const double eps2 = eps * eps;
   float lo, hi;
@@ -241,6 +250,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   bufs.jstar = jstar;
   bufs.list = list;
   bufs.adjT = adjT;
+  bufs.pairs = pairs;
   bufs.st = st;
   dbk::SweepScalars sc{};
   sc.n = ni;
@@ -250,6 +260,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   sc.lo = lo;
   sc.hi = hi;
   sc.eps2 = eps2;
+  sc.edge_cap = L.edge_cap;
+  sc.flags = 0;
+  const bool use_pairs = L.edge_cap > 0;
 
   // ---- step 1 (+ the neighbour counts of step 2)
   const bool bitmask = L.adjacency == DBSCAN_ADJ_BITMASK;
@@ -265,23 +278,43 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     dbk::SweepScalars c1 = sc;
     c1.nchunks = c.nchunks;
     c1.chunk = c.chunk * 64;
-    step(dbk::run_count(bufs, c1, s));
+    step(dbk::run_count(bufs, c1, use_pairs, s));
   }
   mark(1);
   // ---- step 2: core flags
   step(dbk::run_core(counts, ni, npad, minpts, core, corebits, st, s));
   mark(2);
-  // ---- step 3: merge and border assignment
+  // ---- step 3: merge (union-find over core-core neighbour pairs) and border
+  // points (lowest-index core neighbour)
+  const int R = dbk::rows_per_wave(d);
+  const int listed_max = ni;  // every point may be non-core
+  dbk::SweepScalars b3 = sc;
+  {
+    const Chunks c = split(npad / 64, (listed_max + R - 1) / R / 8 + 1, 64LL * L.d_pad * 4, 2);
+    b3.nchunks = c.nchunks;
+    b3.chunk = c.chunk * 64;
+  }
   if (bitmask) {
     const Chunks c = split(npad / 32, npad / 64, 1, 8);
-    dbk::SweepScalars b3 = sc;
-    b3.nchunks = c.nchunks;
-    b3.chunk = c.chunk;
-    step(dbk::run_sweep_bitmask(bufs, b3, s));
+    dbk::SweepScalars u3 = sc;
+    u3.nchunks = c.nchunks;
+    u3.chunk = c.chunk;
+    step(dbk::run_union_bitmask(bufs, u3, s));
+    step(dbk::run_compact_noncore(core, ni, list, st, false, s));
+    step(dbk::run_border(bufs, b3, s));
+  } else if (use_pairs) {
+    // pair list; the repeated sweeps run only if it overflowed
+    step(dbk::run_merge_list(bufs, L.edge_cap, s));
+    dbk::SweepScalars f3 = sc;
+    f3.flags = 1;
+    b3.flags = 1;
+    step(dbk::run_union(bufs, f3, s));
+    step(dbk::run_compact_noncore(core, ni, list, st, true, s));
+    step(dbk::run_border(bufs, b3, s));
   } else {
     step(dbk::run_union(bufs, sc, s));
-    step(dbk::run_compact_noncore(core, ni, list, st, s));
-    step(dbk::run_border(bufs, sc, s));
+    step(dbk::run_compact_noncore(core, ni, list, st, false, s));
+    step(dbk::run_border(bufs, b3, s));
   }
   step(dbk::run_labels(ni, core, jstar, parent, labels, st, s));
   mark(3);
@@ -320,6 +353,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   stats->ms_total = t03;
   stats->thr_lo = lo;
   stats->thr_hi = hi;
+  stats->pairs_listed = (int64_t)hst.edges;
+  stats->pair_overflow = (hst.status & dbk::kStatusEdgeOverflow) ? 1 : 0;
   stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
   return stats->status;
 }

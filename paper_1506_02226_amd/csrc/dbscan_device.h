@@ -17,15 +17,17 @@
 
 namespace dbk {
 
-constexpr unsigned kStatusNonFinite = 1u;
+constexpr unsigned kStatusNonFinite = 1u;     // an input coordinate is NaN or inf
+constexpr unsigned kStatusEdgeOverflow = 2u;  // the neighbour-pair list ran out of room
 
 // Per-call device state (first 256 bytes of the workspace).
 struct DevState {
-  unsigned int status;           // kStatusNonFinite when an input is NaN/inf
+  unsigned int status;           // kStatus* bits
   unsigned int noncore;          // compaction cursor for non-core rows
-  unsigned long long band_pairs; // step-1 pairs re-evaluated in float64
+  unsigned long long band_pairs; // pairs re-evaluated in float64 (all passes)
   unsigned long long core_points;
-  unsigned long long reserved[5];
+  unsigned long long edges;      // pairs (i, j), j < i, appended to the pair list
+  unsigned long long reserved[4];
 };
 
 constexpr int kNoNeighbour = 0x7fffffff;
@@ -33,6 +35,20 @@ constexpr int kNoNeighbour = 0x7fffffff;
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Bits of the 64 columns cb..cb+63 that lie below row i (j < i).
+__device__ __forceinline__ uint64_t below_mask(int i, int cb) {
+  const int lim = i - cb;
+  if (lim <= 0) return 0ull;
+  if (lim >= 64) return ~0ull;
+  return (1ull << lim) - 1ull;
+}
 
 // Exact float64 test of one pair: the definition's own arithmetic.
 template <int D>
@@ -88,15 +104,21 @@ __device__ __forceinline__ uint64_t recheck_band(uint64_t band, uint64_t in, con
 }
 
 // ---------------------------------------------------------------- union-find
+// Reads and path-halving writes are relaxed atomics at work-group scope: they
+// may be served by this XCD's caches and return an older value.  An older
+// value of parent[v] is still an ancestor of v (links are never undone), so
+// every walk stays correct and ends.  Only the hook itself -- a
+// compare-and-swap at device scope on a node that must still be a root --
+// needs the current value, and a failed swap returns it.
 __device__ __forceinline__ int uf_load(const int *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void uf_store(int *p, int v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Root of x with path halving.  parent[v] <= v always holds, so the walk
-// ends; a stale read only returns an older ancestor, which is still valid.
+// ends at a node whose parent is itself.
 __device__ __forceinline__ int uf_find(int *parent, int x) {
   int cur = uf_load(parent + x);
   if (cur != x) {
@@ -111,10 +133,9 @@ __device__ __forceinline__ int uf_find(int *parent, int x) {
   return cur;
 }
 
-// Join the trees of a and b: hook the larger root under the smaller one.
-__device__ __forceinline__ void uf_union(int *parent, int a, int b) {
-  int ra = uf_find(parent, a);
-  int rb = uf_find(parent, b);
+// Join the trees whose (possibly outdated) roots are ra and rb: hook the
+// larger root under the smaller one.  Returns a common ancestor.
+__device__ __forceinline__ int uf_link(int *parent, int ra, int rb) {
   while (ra != rb) {
     if (ra < rb) {
       const int t = ra;
@@ -124,8 +145,72 @@ __device__ __forceinline__ void uf_union(int *parent, int a, int b) {
     int expected = ra;
     if (__hip_atomic_compare_exchange_strong(parent + ra, &expected, rb, __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      return;
+      return rb;
     ra = uf_find(parent, expected);
+  }
+  return ra;
+}
+
+__device__ __forceinline__ void uf_union(int *parent, int a, int b) {
+  uf_link(parent, uf_find(parent, a), uf_find(parent, b));
+}
+
+// ------------------------------------------------------- wave pair queue
+// A wave-private queue of (a, b) pairs in LDS (128 entries).  Ballots fill it
+// from whichever lanes found a pair; it is drained 64 pairs at a time so that
+// every lane of the wave works on one pair (union-find walks are latency
+// bound, so a full wave of independent walks hides the latency).
+struct WaveQueue {
+  int2 *buf;
+  int count;  // wave-uniform
+};
+
+__device__ __forceinline__ void wq_push(WaveQueue &q, bool has, int a, int b) {
+  const uint64_t m = __ballot(has);
+  if (m == 0ull) return;
+  if (has) q.buf[q.count + lanes_below(m)] = make_int2(a, b);
+  q.count += __popcll(m);
+}
+
+__device__ __forceinline__ void wq_pop(WaveQueue &q, int take) {
+  const int lane = lane_id();
+  const int rest = q.count - take;
+  int2 v = make_int2(0, 0);
+  if (lane < rest) v = q.buf[take + lane];
+  if (lane < rest) q.buf[lane] = v;
+  q.count = rest;
+}
+
+// Join the queued pairs (all of them when `all`, else 64 at a time while
+// at least 64 are queued).
+__device__ __forceinline__ void wq_drain_union(WaveQueue &q, int *parent, bool all) {
+  while (q.count >= 64 || (all && q.count > 0)) {
+    const int take = q.count < 64 ? q.count : 64;
+    if (lane_id() < take) {
+      const int2 e = q.buf[lane_id()];
+      uf_union(parent, e.x, e.y);
+    }
+    wq_pop(q, take);
+  }
+}
+
+// Append the queued pairs to the global pair list; past `cap` entries the
+// list is marked as overflowed and the pairs are dropped.
+__device__ __forceinline__ void wq_drain_list(WaveQueue &q, int2 *list, long long cap,
+                                              DevState *st, bool all) {
+  while (q.count >= 64 || (all && q.count > 0)) {
+    const int take = q.count < 64 ? q.count : 64;
+    const int lane = lane_id();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&st->edges, (unsigned long long)take);
+    base = __shfl(base, 0);
+    if (lane < take) {
+      const unsigned long long idx = base + (unsigned long long)lane;
+      if (idx < (unsigned long long)cap) list[idx] = q.buf[lane];
+    }
+    if (lane == 0 && base + (unsigned long long)take > (unsigned long long)cap)
+      atomicOr(&st->status, kStatusEdgeOverflow);
+    wq_pop(q, take);
   }
 }
 

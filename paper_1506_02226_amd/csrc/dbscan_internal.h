@@ -18,6 +18,7 @@ struct Buffers {
   int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
   const int *list;     // [n_pad] compacted non-core rows
   uint32_t *adjT;      // [n_pad/32][n_pad] bitmask adjacency (bitmask form only)
+  int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
   DevState *st;
 };
 
@@ -27,6 +28,8 @@ struct SweepScalars {
   int nchunks, chunk;  // column split: chunk = columns (multiple of 64) or 32-bit words
   float lo, hi;        // float32 band: s <= lo in, s > hi out, else float64
   double eps2;
+  long long edge_cap;  // capacity of the pair list (entries)
+  int flags;           // 1: run only if the pair list overflowed
 };
 
 int rows_per_wave(int d);
@@ -35,15 +38,16 @@ int coord_chunk(int d);
 hipError_t run_reset(DevState *st, hipStream_t s);
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
                      int *parent, int *jstar, DevState *st, hipStream_t s);
-hipError_t run_count(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s);
 hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
                     uint32_t *corebits, DevState *st, hipStream_t s);
 hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
-                               hipStream_t s);
-hipError_t run_sweep_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+                               bool only_on_overflow, hipStream_t s);
+hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
+hipError_t run_union_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
                       const DevState *st, hipStream_t s);
 

@@ -1,0 +1,460 @@
+// Row-uniform sweeps of the on-the-fly form (Section IV-B.1: the distance is
+// fused with the neighbourhood test and never stored).  One wave owns R rows
+// -- the "goal points" of Section IV-A.3, kept in scalar registers for
+// d <= 4 or in LDS otherwise -- and the 64 lanes hold 64 columns, so one
+// compare yields one 64-bit ballot word of the primitive cluster of a row.
+//
+//  * k_count_small: step 1 + counts; also appends every neighbour pair
+//    (i, j), j < i, to a pair list (the input of the merge) while it fits.
+//  * k_union_small / k_border_small: the merge and the border pass repeated
+//    on the fly; they run only when the pair list overflowed (or always, for
+//    the border pass of the bitmask form).
+//  * k_rows_lds: the three sweeps for d > 4 (no pair list).
+#include "dbscan_device.h"
+#include "dbscan_internal.h"
+
+namespace dbk {
+
+constexpr int kOnlyOnOverflow = 1;
+
+__device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevState *st) {
+  if (!(sc.flags & kOnlyOnOverflow)) return false;
+  return !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+           kStatusEdgeOverflow);
+}
+
+// Lanes of the band (m & ~in) re-decided in float64; returns the exact mask.
+template <int D>
+__device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const float (&a)[D],
+                                                const float (&b)[D], double eps2, DevState *st) {
+  if (in == m) return in;
+  return recheck_band<D>(m & ~in, in, a, b, eps2, st);
+}
+
+// ------------------------------------------------- step 1 + counts, d <= 4
+template <int D, int R, bool EMIT>
+__global__ __launch_bounds__(256) void k_count_small(const float *__restrict__ soa,
+                                                     int *__restrict__ counts,
+                                                     int2 *__restrict__ pairs,
+                                                     DevState *__restrict__ st, SweepScalars sc) {
+  __shared__ int2 qbuf[4][128];
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int chunk = blockIdx.x % sc.nchunks;
+  const int row0 = ((blockIdx.x / sc.nchunks) * 4 + w) * R;
+  if (row0 >= sc.n) return;
+  const int c0 = chunk * sc.chunk;
+  const int c1 = min(c0 + sc.chunk, sc.n_pad);
+  float xr[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+  int cnt[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) cnt[r] = 0;
+  WaveQueue qu{qbuf[w], 0};
+  float xn[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + c0 + lane];
+  for (int cb = c0; cb < c1; cb += 64) {
+    float xc[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xc[k] = xn[k];
+    if (cb + 64 < c1) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float s = sq_dist32<D>(xr[r], xc);
+      const uint64_t m = __ballot(s <= sc.hi);
+      if (m != 0ull) {
+        const uint64_t in = settle_band<D>(m, __ballot(s <= sc.lo), xr[r], xc, sc.eps2, st);
+        cnt[r] += __popcll(in);
+        if (EMIT) {
+          const uint64_t e = in & below_mask(row0 + r, cb);
+          if (e != 0ull) {
+            wq_push(qu, (e >> lane) & 1ull, row0 + r, cb + lane);
+            wq_drain_list(qu, pairs, sc.edge_cap, st, false);
+          }
+        }
+      }
+    }
+  }
+  if (EMIT) wq_drain_list(qu, pairs, sc.edge_cap, st, true);
+  int mine = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane == r) mine = cnt[r];
+  const int row = row0 + lane;
+  if (lane < R && row < sc.n) {
+    if (sc.nchunks == 1)
+      counts[row] = mine;
+    else
+      atomicAdd(counts + row, mine);
+  }
+}
+
+// --------------------------------------- merge repeated on the fly, d <= 4
+// Core rows i queue their core neighbours j < i; the queue is drained into
+// the union-find 64 pairs at a time.
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_union_small(const float *__restrict__ soa,
+                                                     const uint32_t *__restrict__ corebits,
+                                                     int *__restrict__ parent,
+                                                     DevState *__restrict__ st, SweepScalars sc) {
+  __shared__ int2 qbuf[4][128];
+  if (skip_sweep(sc, st)) return;
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int total = (sc.n + R - 1) / R;
+  const int rb = total - 1 - (int)(blockIdx.x * 4 + w);  // longest rows first
+  if (rb < 0) return;
+  const int row0 = rb * R;
+  uint32_t active = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = row0 + r;
+    if (i < sc.n && ((corebits[i >> 5] >> (i & 31)) & 1u)) active |= 1u << r;
+  }
+  if (active == 0u) return;
+  const int last = row0 + 31 - __builtin_clz(active);
+  const int c1 = ((last + 63) >> 6) << 6;  // columns j < last
+  float xr[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+  WaveQueue qu{qbuf[w], 0};
+  for (int cb = 0; cb < c1; cb += 64) {
+    const uint64_t cw = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
+    if (cw == 0ull) continue;
+    float xc[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xc[k] = soa[(size_t)k * sc.n_pad + cb + lane];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!((active >> r) & 1u)) continue;
+      const uint64_t cm = cw & below_mask(row0 + r, cb);
+      if (cm == 0ull) continue;
+      const float s = sq_dist32<D>(xr[r], xc);
+      const uint64_t m = __ballot(s <= sc.hi) & cm;
+      if (m != 0ull) {
+        const uint64_t in =
+            settle_band<D>(m, __ballot(s <= sc.lo) & cm, xr[r], xc, sc.eps2, st);
+        wq_push(qu, (in >> lane) & 1ull, row0 + r, cb + lane);
+        wq_drain_union(qu, parent, false);
+      }
+    }
+  }
+  wq_drain_union(qu, parent, true);
+}
+
+// ----------------------------------- border points repeated on the fly, d <= 4
+// Work item = (group of R listed non-core rows, column chunk); a persistent
+// grid strides over the items.  Each item records the first core neighbour
+// in its chunk with atomicMin, so the lowest-index one survives.
+template <int D, int R>
+__global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ soa,
+                                                      const uint32_t *__restrict__ corebits,
+                                                      const int *__restrict__ list,
+                                                      int *__restrict__ jstar,
+                                                      DevState *__restrict__ st, SweepScalars sc) {
+  if (skip_sweep(sc, st)) return;
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int listed = wave_uniform((int)__hip_atomic_load(&st->noncore, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT));
+  const int groups = (listed + R - 1) / R;
+  const int items = groups * sc.nchunks;
+  const int nwaves = gridDim.x * 4;
+  for (int item = blockIdx.x * 4 + w; item < items; item += nwaves) {
+    const int chunk = item % sc.nchunks;
+    const int e0 = (item / sc.nchunks) * R;
+    int rows[R];
+    uint32_t active = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rows[r] = 0;
+      if (e0 + r < listed) {
+        rows[r] = wave_uniform(list[e0 + r]);
+        active |= 1u << r;
+      }
+    }
+    float xr[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + rows[r]];
+    int found[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) found[r] = kNoNeighbour;
+    const int c0 = chunk * sc.chunk;
+    const int c1 = min(c0 + sc.chunk, sc.n_pad);
+    for (int cb = c0; cb < c1 && active != 0u; cb += 64) {
+      const uint64_t cw = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
+      if (cw == 0ull) continue;
+      float xc[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) xc[k] = soa[(size_t)k * sc.n_pad + cb + lane];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!((active >> r) & 1u)) continue;
+        const float s = sq_dist32<D>(xr[r], xc);
+        const uint64_t m = __ballot(s <= sc.hi) & cw;
+        if (m != 0ull) {
+          const uint64_t in =
+              settle_band<D>(m, __ballot(s <= sc.lo) & cw, xr[r], xc, sc.eps2, st);
+          if (in != 0ull) {
+            found[r] = cb + __builtin_ctzll(in);
+            active &= ~(1u << r);
+          }
+        }
+      }
+    }
+    int mine = kNoNeighbour, myrow = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane == r) {
+        mine = found[r];
+        myrow = rows[r];
+      }
+    if (lane < R && mine != kNoNeighbour) atomicMin(jstar + myrow, mine);
+  }
+}
+
+// ---------------------------------------------- row-uniform sweeps, any d
+// Rows staged in LDS ([4 waves][R][d_pad], read as broadcasts), columns in
+// lanes, coordinates processed DC at a time.  Same three modes as above.
+enum { MODE_COUNT = 0, MODE_UNION = 1, MODE_BORDER = 2 };
+
+template <int DC, int R, int MODE>
+__global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
+                                                  int *__restrict__ counts,
+                                                  const uint32_t *__restrict__ corebits,
+                                                  int *__restrict__ parent,
+                                                  const int *__restrict__ list,
+                                                  int *__restrict__ jstar,
+                                                  DevState *__restrict__ st, SweepScalars sc) {
+  extern __shared__ float lds_rows[];
+  if (skip_sweep(sc, st)) return;
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int n = sc.n;
+  int rows[R];
+  uint32_t active = 0;
+  int cb_begin = 0, cb_end = sc.n_pad;
+  if (MODE == MODE_COUNT) {
+    const int chunk = blockIdx.x % sc.nchunks;
+    const int rb = (blockIdx.x / sc.nchunks) * 4 + w;
+    cb_begin = chunk * sc.chunk;
+    cb_end = min(cb_begin + sc.chunk, sc.n_pad);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rows[r] = rb * R + r;
+      if (rows[r] < n) active |= 1u << r;
+    }
+  } else if (MODE == MODE_UNION) {
+    const int total = (n + R - 1) / R;
+    const int rb = total - 1 - (int)(blockIdx.x * 4 + w);
+    int last = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rows[r] = rb * R + r;
+      if (rb >= 0 && rows[r] < n && ((corebits[rows[r] >> 5] >> (rows[r] & 31)) & 1u)) {
+        active |= 1u << r;
+        last = rows[r];
+      }
+    }
+    cb_end = min(((last + 63) / 64) * 64, sc.n_pad);
+  } else {
+    const int listed = wave_uniform((int)__hip_atomic_load(&st->noncore, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+    const int e0 = (blockIdx.x * 4 + w) * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      rows[r] = 0;
+      if (e0 + r < listed) {
+        rows[r] = wave_uniform(list[e0 + r]);
+        active |= 1u << r;
+      }
+    }
+  }
+  float *my_rows = lds_rows + (size_t)w * R * sc.d_pad;
+  for (int e = lane; e < R * sc.d_pad; e += 64) {
+    const int r = e / sc.d_pad, k = e - r * sc.d_pad;
+    float v = 0.0f;
+    if ((active >> r) & 1u) v = soa[(size_t)k * sc.n_pad + rows[r]];
+    my_rows[e] = v;
+  }
+  __syncthreads();
+
+  int acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = (MODE == MODE_BORDER) ? kNoNeighbour : 0;
+
+  for (int cb = cb_begin; cb < cb_end; cb += 64) {
+    if (MODE != MODE_COUNT && active == 0u) break;
+    uint64_t colmask = ~0ull;
+    if (MODE != MODE_COUNT) {
+      colmask = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
+      if (colmask == 0ull) continue;
+    }
+    const int j = cb + lane;
+    float s[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) s[r] = 0.0f;
+    for (int kc = 0; kc < sc.d_pad; kc += DC) {
+      float xc[DC];
+#pragma unroll
+      for (int k = 0; k < DC; ++k) xc[k] = soa[(size_t)(kc + k) * sc.n_pad + j];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float *xrow = my_rows + r * sc.d_pad + kc;
+        float a = s[r];
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+          const float t = xrow[k] - xc[k];
+          a = __builtin_fmaf(t, t, a);
+        }
+        s[r] = a;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!((active >> r) & 1u)) continue;
+      uint64_t cm = colmask;
+      if (MODE == MODE_UNION) {
+        const int lim = rows[r] - cb;
+        if (lim <= 0) continue;
+        if (lim < 64) cm &= (1ull << lim) - 1ull;
+      }
+      const uint64_t m = __ballot(s[r] <= sc.hi) & cm;
+      if (m == 0ull) continue;
+      uint64_t in = __ballot(s[r] <= sc.lo) & cm;
+      if (in != m) {
+        const uint64_t band = m & ~in;
+        bool ex = false;
+        if ((band >> lane) & 1ull)
+          ex = exact_within_mem(my_rows + r * sc.d_pad, 1, soa + j, sc.n_pad, sc.d, sc.eps2);
+        in |= __ballot(ex);
+        if (lane == 0) atomicAdd(&st->band_pairs, (unsigned long long)__popcll(band));
+      }
+      if (MODE == MODE_COUNT) {
+        acc[r] += __popcll(in);
+      } else if (MODE == MODE_UNION) {
+        if ((in >> lane) & 1ull) uf_union(parent, rows[r], j);
+      } else if (in != 0ull) {
+        acc[r] = cb + __builtin_ctzll(in);
+        active &= ~(1u << r);
+      }
+    }
+  }
+  if (MODE == MODE_UNION) return;
+  int mine = 0, myrow = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (lane == r) {
+      mine = acc[r];
+      myrow = rows[r];
+    }
+  if (MODE == MODE_COUNT) {
+    if (lane < R && myrow < n) {
+      if (sc.nchunks == 1)
+        counts[myrow] = mine;
+      else
+        atomicAdd(counts + myrow, mine);
+    }
+  } else if (lane < R && mine != kNoNeighbour) {
+    atomicMin(jstar + myrow, mine);
+  }
+}
+
+// ------------------------------------------------------------ host launchers
+constexpr int kRowsSmall = 8;  // rows per wave, d <= 4 (scalar registers)
+constexpr int kRowsLds = 8;    // rows per wave, d > 4 (LDS)
+
+int rows_per_wave(int d) { return d <= 4 ? kRowsSmall : kRowsLds; }
+
+int coord_chunk(int d) {
+  if (d <= 4) return d;
+  if (d <= 8) return 8;
+  if (d <= 16) return 16;
+  if (d <= 32) return 32;
+  return 64;
+}
+
+template <int MODE>
+static hipError_t launch_lds(const Buffers &b, const SweepScalars &sc, int blocks, hipStream_t s) {
+  const size_t lds = (size_t)4 * kRowsLds * sc.d_pad * sizeof(float);
+  switch (coord_chunk(sc.d)) {
+#define DBK_LDS_CASE(DC)                                                                      \
+  case DC:                                                                                    \
+    hipLaunchKernelGGL((k_rows_lds<DC, kRowsLds, MODE>), dim3(blocks), dim3(256), lds, s,    \
+                       b.soa, b.counts, b.corebits, b.parent, b.list, b.jstar, b.st, sc);     \
+    break;
+    DBK_LDS_CASE(8)
+    DBK_LDS_CASE(16)
+    DBK_LDS_CASE(32)
+    DBK_LDS_CASE(64)
+#undef DBK_LDS_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s) {
+  const int R = rows_per_wave(sc.d);
+  const int groups = ((sc.n + R - 1) / R + 3) / 4;
+  const dim3 grid(groups * sc.nchunks), block(256);
+#define DBK_COUNT(D)                                                                          \
+  if (emit_pairs)                                                                             \
+    hipLaunchKernelGGL((k_count_small<D, kRowsSmall, true>), grid, block, 0, s, b.soa,       \
+                       b.counts, b.pairs, b.st, sc);                                          \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_count_small<D, kRowsSmall, false>), grid, block, 0, s, b.soa,      \
+                       b.counts, b.pairs, b.st, sc);                                          \
+  break;
+  switch (sc.d) {
+    case 1: DBK_COUNT(1)
+    case 2: DBK_COUNT(2)
+    case 3: DBK_COUNT(3)
+    case 4: DBK_COUNT(4)
+    default: return launch_lds<MODE_COUNT>(b, sc, (int)grid.x, s);
+  }
+#undef DBK_COUNT
+  return hipGetLastError();
+}
+
+hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
+  const int R = rows_per_wave(sc.d);
+  const dim3 grid(((sc.n + R - 1) / R + 3) / 4), block(256);
+  switch (sc.d) {
+    case 1: hipLaunchKernelGGL((k_union_small<1, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.parent, b.st, sc); break;
+    case 2: hipLaunchKernelGGL((k_union_small<2, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.parent, b.st, sc); break;
+    case 3: hipLaunchKernelGGL((k_union_small<3, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.parent, b.st, sc); break;
+    case 4: hipLaunchKernelGGL((k_union_small<4, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.parent, b.st, sc); break;
+    default: return launch_lds<MODE_UNION>(b, sc, (int)grid.x, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
+  const int R = rows_per_wave(sc.d);
+  if (sc.d > 4) {
+    const int blocks = ((sc.n + R - 1) / R + 3) / 4;
+    return launch_lds<MODE_BORDER>(b, sc, blocks, s);
+  }
+  const dim3 grid(4096), block(256);
+  switch (sc.d) {
+    case 1: hipLaunchKernelGGL((k_border_small<1, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
+    case 2: hipLaunchKernelGGL((k_border_small<2, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
+    case 3: hipLaunchKernelGGL((k_border_small<3, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
+    case 4: hipLaunchKernelGGL((k_border_small<4, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dbk

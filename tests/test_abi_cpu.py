@@ -68,12 +68,20 @@ def test_workspace_size_layout():
     assert L.dbscan_workspace_size(200_000, 2, ctypes.byref(bm), ctypes.byref(out)) == 0
     n_pad = 200_192
     assert out.value >= n_pad * n_pad // 8
+    # on the fly: O(n d) plus the pair list (8 bytes per pair, 128 pairs per point by default)
     fly = _lib.make_opts("onthefly")
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(fly), ctypes.byref(out)) == 0
-    assert out.value < 64 * 2_000_128  # O(n d)
-    auto = _lib.make_opts("auto")
+    base = out.value - 8 * 128 * 2_000_000
+    assert 0 < base < 64 * 2_000_128
+    auto = _lib.make_opts("auto")  # picks on the fly: the bitmask would be 500 GB
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(auto), ctypes.byref(out)) == 0
-    assert out.value < 64 * 2_000_128  # auto picks on-the-fly: bitmask would be 500 GB
+    assert out.value == base + 8 * 128 * 2_000_000
+    small = _lib.make_opts("onthefly", pair_capacity=1000)
+    assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(small), ctypes.byref(out)) == 0
+    assert out.value == base + 8 * 1024  # 1000 pairs, rounded up to 256 bytes
+    wide = _lib.make_opts("onthefly")  # d > 4: no pair list
+    assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(wide), ctypes.byref(out)) == 0
+    assert out.value < 32 * 100_096 * 4
 
 
 def _band(eps2, d):

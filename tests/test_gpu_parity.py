@@ -222,3 +222,17 @@ def test_aniso3d_2m_full_size():
     rows = np.sort(rng.choice(w.n, 16, replace=False))
     rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]])
     _sampled_checks(w, gpu, rows)
+
+
+@pytest.mark.parametrize("cap", [1, 100, 0])
+def test_pair_list_overflow_falls_back(cap):
+    """The on-the-fly form records neighbour pairs for the merge; when they do
+    not fit it repeats the epsilon tests instead, with identical results."""
+    w = wl.aniso3d_2m(0, n=20_000)
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    gpu = run(w.points, w.eps, w.minpts, adjacency="onthefly", pair_capacity=cap, stats=True)
+    assert_same(gpu, ref, f"cap={cap}")
+    st = gpu[3]
+    half_edges = (int(ref[2].sum()) - w.n) // 2
+    assert st["pairs_listed"] == half_edges
+    assert st["pair_overflow"] == (1 if 0 < cap < half_edges else 0)
