@@ -34,6 +34,7 @@ if ROOT not in sys.path:
 # so the one-per-SIMD-every-4-clocks figure (39.3e12) is not a ceiling.
 VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
 HBM_PEAK_BYTES = 8.0e12
+MFMA_16BIT_PEAK = 2.5e15  # dense BF16/FP16 matrix-core FLOP/s
 
 
 def valu_ops_per_pair(d: int) -> int:
@@ -98,6 +99,7 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blobs2d_200k")
     ap.add_argument("--adjacency", default="auto", choices=["auto", "bitmask", "onthefly"])
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample", type=int, default=80_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args(argv)
@@ -120,23 +122,22 @@ def main(argv=None) -> int:
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     core = torch.empty(n, dtype=torch.uint8, device=dev)
     counts = torch.empty(n, dtype=torch.int32, device=dev)
-    ws_bytes = pkg.workspace_size(n, d, args.adjacency)
+    ws_bytes = pkg.workspace_size(n, d, args.adjacency, args.precision)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     out = (labels, core, counts)
 
     # one checked call first: statistics (adjacency used, band pairs)
-    _, _, _, st = pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, stats=True, out=out,
-                          workspace=ws)
+    kw = dict(adjacency=args.adjacency, precision=args.precision, out=out, workspace=ws)
+    _, _, _, st = pkg.fit(x, w.eps, w.minpts, stats=True, **kw)
 
     hip = HipEvents()
     ev = [hip.block(4) for _ in range(args.steps)]
     for _ in range(args.warmup):
-        pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, out=out, workspace=ws)
+        pkg.fit(x, w.eps, w.minpts, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        pkg.fit(x, w.eps, w.minpts, adjacency=args.adjacency, out=out, workspace=ws,
-                events=ctypes.addressof(ev[k]))
+        pkg.fit(x, w.eps, w.minpts, events=ctypes.addressof(ev[k]), **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) / args.steps * 1e3
@@ -148,9 +149,21 @@ def main(argv=None) -> int:
 
     pairs = float(n) * float(n)
     k_ms = float(np.mean(s1))
-    achieved = pairs * valu_ops_per_pair(d) / (k_ms * 1e-3) / 1e12
-    peak = VALU_LANE_OPS_PEAK / 1e12
-    kernel = "k_bitmask" if st["adjacency_used"] == "bitmask" else "k_count_small"
+    if st["precision_used"] in ("bf16", "fp16"):
+        # matrix cores: 2d FLOPs per ordered pair (the dot product x_i . x_j)
+        achieved = pairs * 2 * d / (k_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "k_mfma_count", "achieved": round(achieved, 3),
+                "peak": MFMA_16BIT_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": round(achieved * 1e12 / MFMA_16BIT_PEAK, 4), "traffic": None,
+                "flops_per_pair": 2 * d}
+    else:
+        achieved = pairs * valu_ops_per_pair(d) / (k_ms * 1e-3) / 1e12
+        kernel = "k_bitmask" if st["adjacency_used"] == "bitmask" else (
+            "k_count_small" if d <= 4 else "k_rows_lds")
+        roof = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
+                "peak": round(VALU_LANE_OPS_PEAK / 1e12, 3), "unit": "Tlane-op/s",
+                "frac": round(achieved * 1e12 / VALU_LANE_OPS_PEAK, 4), "traffic": None,
+                "ops_per_pair": valu_ops_per_pair(d)}
     rec = {
         "metric": "eps-pair tests/sec (Gpairs/s) + points clustered/s",
         "value": round(pairs / (ms_step * 1e-3) / 1e9, 3),
@@ -172,11 +185,9 @@ def main(argv=None) -> int:
         "phase_ms": {"step1": round(k_ms, 4), "step2": round(float(np.mean(s2)), 4),
                      "step3": round(float(np.mean(s3)), 4)},
         "pairs_rechecked_fp64": int(st["pairs_rechecked"]),
+        "pairs_listed": int(st["pairs_listed"]),
         "core_points": int(st["core_points"]),
-        "roofline": {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
-                     "peak": round(peak, 3), "unit": "Tlane-op/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
-                     "ops_per_pair": valu_ops_per_pair(d)},
+        "roofline": roof,
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

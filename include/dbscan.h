@@ -69,10 +69,11 @@ extern "C" {
 #define DBSCAN_ADJ_ONTHEFLY 2 /* nothing stored; step 3 repeats the epsilon tests */
 
 /* Arithmetic of the epsilon-test filter (the decision is always float64-exact). */
-#define DBSCAN_PREC_AUTO 0 /* float32 for d < 16, FP16 matrix cores for d >= 16 */
+#define DBSCAN_PREC_AUTO 0 /* FP16 matrix cores for 16 <= d <= 76, else float32 */
 #define DBSCAN_PREC_FP32 1 /* float32 direct form (x_i - x_j)^2 summed */
-#define DBSCAN_PREC_BF16 2 /* |x|^2 + |y|^2 - 2 x.y on BF16 matrix cores, d >= 16 */
-#define DBSCAN_PREC_FP16 3 /* |x|^2 + |y|^2 - 2 x.y on FP16 matrix cores, d >= 16 */
+#define DBSCAN_PREC_BF16 2 /* |x|^2 + |y|^2 - 2 x.y on BF16 matrix cores, d <= 76 */
+#define DBSCAN_PREC_FP16 3 /* same on FP16 matrix cores, d <= 76; inputs with
+                              |x| > 30000 or |x|^2 > 30000 fall back to float32 */
 
 typedef struct dbscan_opts {
   int32_t adjacency;          /* DBSCAN_ADJ_*  (0 = auto) */
@@ -91,6 +92,10 @@ typedef struct dbscan_opts {
                                  for the merge (8 bytes each; 0 = 128 per point).
                                  If they do not fit, step 3 repeats the epsilon
                                  tests instead; results are identical. */
+  uint64_t band_capacity;     /* matrix-core filter: room for this many undecided
+                                 pairs awaiting the float64 pass (8 bytes each;
+                                 0 = 64 per point).  If they do not fit, step 1
+                                 is redone with the float32 direct form. */
   void *events;               /* HOST, optional: hipEvent_t[4] created by the caller.
                                  Recorded on `stream` (no wait) before the step-1
                                  kernel and after steps 1, 2 and 3, so the caller
@@ -109,11 +114,14 @@ typedef struct dbscan_stats {
   float ms_step2;         /* core flags */
   float ms_step3;         /* merge, border assignment and labels */
   float ms_total;         /* steps 1-3, device time (input staging excluded) */
-  float thr_lo, thr_hi;   /* float32 band thresholds used by the direct form */
+  float thr_lo, thr_hi;   /* band thresholds of the filter used (float32 direct
+                             form on s32, or matrix-core form on s~) */
   int64_t pairs_listed;   /* neighbour pairs j < i found by step 1 (pair list) */
   int32_t pair_overflow;  /* 1 if they exceeded pair_capacity (step 3 repeated
                              the tests), else 0 */
-  int32_t reserved;
+  int32_t filter_fallback;/* 1 if the matrix-core filter gave up (inputs out of
+                             its range or band_capacity exceeded) and step 1 was
+                             redone in float32, else 0 */
 } dbscan_stats;
 
 /*

@@ -28,10 +28,10 @@ def version() -> int:
 
 
 def workspace_size(n: int, d: int, adjacency: str = "auto", precision: str = "auto",
-                   bitmask_limit: int = 0, pair_capacity: int = 0) -> int:
+                   bitmask_limit: int = 0, pair_capacity: int = 0, band_capacity: int = 0) -> int:
     L = _lib.load()
     opts = _lib.make_opts(adjacency, precision, bitmask_limit=bitmask_limit,
-                          pair_capacity=pair_capacity)
+                          pair_capacity=pair_capacity, band_capacity=band_capacity)
     out = ctypes.c_uint64(0)
     rc = L.dbscan_workspace_size(int(n), int(d), ctypes.byref(opts), ctypes.byref(out))
     if rc != _lib.DBSCAN_OK:
@@ -52,7 +52,7 @@ def _check_points(points):
 
 def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: str = "auto",
         band_rel: float = 0.0, bitmask_limit: int = 0, pair_capacity: int = 0,
-        stats: bool = False, out=None, workspace=None, events: int = 0):
+        band_capacity: int = 0, stats: bool = False, out=None, workspace=None, events: int = 0):
     """Cluster `points` (torch float32 (n, d) on the GPU).
 
     Returns (labels int32[n], core uint8[n], counts int32[n]) as GPU tensors,
@@ -72,14 +72,15 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
         counts = torch.empty(n, dtype=torch.int32, device=dev)
     else:
         labels, core, counts = out
-    ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit, pair_capacity)
+    ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit, pair_capacity,
+                              band_capacity)
     if workspace is None:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) // 256 * 256
     avail = workspace.numel() - (aligned - base)
     opts = _lib.make_opts(adjacency, precision, band_rel, bitmask_limit, aligned, avail, events,
-                          pair_capacity)
+                          pair_capacity, band_capacity)
     st = _lib.Stats()
     stream = torch.cuda.current_stream(dev).cuda_stream
     with torch.cuda.device(dev):

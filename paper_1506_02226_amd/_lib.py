@@ -46,6 +46,7 @@ class Opts(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
         ("pair_capacity", ctypes.c_uint64),
+        ("band_capacity", ctypes.c_uint64),
         ("events", ctypes.c_void_p),
     ]
 
@@ -67,7 +68,7 @@ class Stats(ctypes.Structure):
         ("thr_hi", ctypes.c_float),
         ("pairs_listed", ctypes.c_int64),
         ("pair_overflow", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("filter_fallback", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -121,7 +122,7 @@ def load(path: str | None = None):
 
 def make_opts(adjacency: str = "auto", precision: str = "auto", band_rel: float = 0.0,
               bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0,
-              events: int = 0, pair_capacity: int = 0) -> Opts:
+              events: int = 0, pair_capacity: int = 0, band_capacity: int = 0) -> Opts:
     return Opts(ADJ[adjacency], PREC[precision], float(band_rel), int(bitmask_limit),
                 int(workspace) or None, int(workspace_bytes), int(pair_capacity),
-                int(events) or None)
+                int(band_capacity), int(events) or None)

@@ -15,6 +15,10 @@ __global__ void k_reset_state(DevState *st) {
     st->band_pairs = 0;
     st->core_points = 0;
     st->edges = 0;
+    st->band_list = 0;
+    st->max_norm = 0;
+    st->thr[0] = 0.0f;
+    st->thr[1] = 0.0f;
   }
 }
 
@@ -128,6 +132,19 @@ __global__ void k_labels(int n, const uint8_t *__restrict__ core, const int *__r
   }
 }
 
+// ----------------------------------------------------- filter fallback
+// When the matrix-core filter gave up (inputs out of its range, or too many
+// undecided pairs), clear the counts for the float32 sweep that redoes step 1
+// and mark the pair list as incomplete so that step 3 repeats the tests.
+__global__ void k_filter_fallback(int *__restrict__ counts, int n, DevState *st) {
+  const unsigned status =
+      __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!(status & (kStatusRange | kStatusBandOverflow))) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) counts[i] = 0;
+  if (i == 0) atomicOr(&st->status, kStatusEdgeOverflow);
+}
+
 // ------------------------------------------------------------ host launchers
 hipError_t run_reset(DevState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st);
@@ -158,6 +175,11 @@ hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s) {
   hipLaunchKernelGGL(k_merge_list, dim3(2048), dim3(256), 0, s, b.pairs, b.corebits, b.parent,
                      b.jstar, b.st, cap);
+  return hipGetLastError();
+}
+
+hipError_t run_filter_fallback(int *counts, int n, DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_fallback, dim3((n + 255) / 256), dim3(256), 0, s, counts, n, st);
   return hipGetLastError();
 }
 

@@ -17,8 +17,11 @@ constexpr int kVersion = 100;  // 0.1.0
 constexpr int64_t kPadRows = 256;
 constexpr int32_t kMaxD = 1024;
 constexpr uint64_t kDefaultBitmaskLimit = 16ull << 30;
+constexpr double kDefaultBandRel = 1e-2;
 constexpr uint64_t kPairsPerPoint = 128;       // default pair-list capacity per point
 constexpr uint64_t kMaxPairs = 2147483647ull;  // 16 GiB of (int, int) pairs
+constexpr uint64_t kBandPerPoint = 64;         // default band-list capacity per point
+constexpr int32_t kMaxMfmaD = 76;              // contraction d + 4 <= 80
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -28,8 +31,11 @@ struct Layout {
   int adjacency = DBSCAN_ADJ_ONTHEFLY;
   int precision = DBSCAN_PREC_FP32;
   uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
-           off_list = 0, off_adj = 0, off_pairs = 0, total = 0;
-  int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4)
+           off_list = 0, off_adj = 0, off_pairs = 0, off_aaug = 0, off_baug = 0, off_band = 0,
+           total = 0;
+  int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4 or matrix cores)
+  int64_t band_cap = 0;  // band-list entries (matrix cores)
+  int mfma_k = 0;        // contraction length of the matrix-core filter
 };
 
 uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
@@ -41,13 +47,19 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   const int req_adj = o ? o->adjacency : DBSCAN_ADJ_AUTO;
   const int req_prec = o ? o->precision : DBSCAN_PREC_AUTO;
   const uint64_t limit = (o && o->bitmask_limit) ? o->bitmask_limit : kDefaultBitmaskLimit;
-  if (req_prec == DBSCAN_PREC_AUTO || req_prec == DBSCAN_PREC_FP32)
+  const bool mfma_ok = d <= kMaxMfmaD;
+  if (req_prec == DBSCAN_PREC_AUTO)
+    L->precision = (d >= 16 && mfma_ok && req_adj != DBSCAN_ADJ_BITMASK) ? DBSCAN_PREC_FP16
+                                                                         : DBSCAN_PREC_FP32;
+  else if (req_prec == DBSCAN_PREC_FP32)
     L->precision = DBSCAN_PREC_FP32;
-  else if (req_prec == DBSCAN_PREC_BF16 || req_prec == DBSCAN_PREC_FP16)
-    return DBSCAN_E_UNSUPPORTED;
-  else
+  else if (req_prec == DBSCAN_PREC_BF16 || req_prec == DBSCAN_PREC_FP16) {
+    if (!mfma_ok) return DBSCAN_E_UNSUPPORTED;
+    L->precision = req_prec;
+  } else
     return DBSCAN_E_INVAL;
-  const bool bm_ok = d <= 4;
+  const bool mfma = L->precision != DBSCAN_PREC_FP32;
+  const bool bm_ok = d <= 4 && !mfma;
   if (req_adj == DBSCAN_ADJ_BITMASK) {
     if (!bm_ok) return DBSCAN_E_UNSUPPORTED;
     L->adjacency = DBSCAN_ADJ_BITMASK;
@@ -72,11 +84,19 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->off_corebits = take((uint64_t)L->n_pad / 8);
   L->off_list = take((uint64_t)L->n_pad * 4);
   L->off_adj = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(bitmask_bytes(L->n_pad)) : off;
-  if (L->adjacency == DBSCAN_ADJ_ONTHEFLY && d <= 4) {
+  if (L->adjacency == DBSCAN_ADJ_ONTHEFLY && (d <= 4 || mfma)) {
     const uint64_t req = (o && o->pair_capacity) ? o->pair_capacity : (uint64_t)kPairsPerPoint * n;
     L->edge_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
   }
   L->off_pairs = L->edge_cap ? take((uint64_t)L->edge_cap * 8) : off;
+  if (mfma) {
+    L->mfma_k = dbk::mfma_k(d);
+    L->off_aaug = take((uint64_t)L->n_pad * L->mfma_k * 2);
+    L->off_baug = take((uint64_t)L->n_pad * L->mfma_k * 2);
+    const uint64_t req = (o && o->band_capacity) ? o->band_capacity : (uint64_t)kBandPerPoint * n;
+    L->band_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
+    L->off_band = take((uint64_t)L->band_cap * 8);
+  }
   L->total = off;
   return DBSCAN_OK;
 }
@@ -214,6 +234,10 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   auto *list = (int *)(ws + L.off_list);
   auto *adjT = (uint32_t *)(ws + L.off_adj);
   auto *pairs = (int2 *)(ws + L.off_pairs);
+  void *a_aug = ws + L.off_aaug;
+  void *b_aug = ws + L.off_baug;
+  auto *band = (int2 *)(ws + L.off_band);
+  const bool mfma = L.precision != DBSCAN_PREC_FP32;
 
   const double eps2 = eps * eps;
   float lo, hi;
@@ -240,6 +264,11 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
 
   step(dbk::run_reset(st, s));
   step(dbk::run_stage(points, ni, d, npad, L.d_pad, soa, counts, parent, jstar, st, s));
+  const double band_rel = (opts && opts->band_rel > 0.0) ? opts->band_rel : kDefaultBandRel;
+  if (mfma) {
+    step(dbk::run_mfma_prep(points, ni, d, npad, L.precision, a_aug, b_aug, st, s));
+    step(dbk::run_mfma_thresholds(st, eps * eps, d, L.precision, band_rel, s));
+  }
   mark(0);
 
   dbk::Buffers bufs{};
@@ -251,6 +280,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   bufs.list = list;
   bufs.adjT = adjT;
   bufs.pairs = pairs;
+  bufs.band = band;
   bufs.st = st;
   dbk::SweepScalars sc{};
   sc.n = ni;
@@ -266,7 +296,28 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
 
   // ---- step 1 (+ the neighbour counts of step 2)
   const bool bitmask = L.adjacency == DBSCAN_ADJ_BITMASK;
-  if (bitmask) {
+  if (mfma) {
+    dbk::MfmaScalars ms{};
+    ms.n = ni;
+    ms.n_pad = npad;
+    ms.d = d;
+    const Chunks c = split(npad / 32, npad / 256 * 4, 32LL * L.mfma_k * 2, 4);
+    ms.nchunks = c.nchunks;
+    ms.chunk = c.chunk;
+    ms.pair_cap = L.edge_cap;
+    ms.band_cap = L.band_cap;
+    step(dbk::run_mfma_count(a_aug, b_aug, bufs, ms, L.precision, s));
+    step(dbk::run_recheck_band(points, d, bufs, eps2, L.band_cap, L.edge_cap, s));
+    // the float32 sweep redoes step 1 only if the filter gave up
+    step(dbk::run_filter_fallback(counts, ni, st, s));
+    const int R = dbk::rows_per_wave(d);
+    const Chunks cf = split(npad / 64, (n + R - 1) / R, 64LL * L.d_pad * 4, 2);
+    dbk::SweepScalars f1 = sc;
+    f1.nchunks = cf.nchunks;
+    f1.chunk = cf.chunk * 64;
+    f1.flags = dbk::kOnlyOnFilterFail;
+    step(dbk::run_count(bufs, f1, false, s));
+  } else if (bitmask) {
     const Chunks c = split(npad / 32, npad / 64, 32LL * d * 4, 2);
     dbk::SweepScalars b1 = sc;
     b1.nchunks = c.nchunks;
@@ -306,8 +357,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     // pair list; the repeated sweeps run only if it overflowed
     step(dbk::run_merge_list(bufs, L.edge_cap, s));
     dbk::SweepScalars f3 = sc;
-    f3.flags = 1;
-    b3.flags = 1;
+    f3.flags = dbk::kOnlyOnOverflow;
+    b3.flags = dbk::kOnlyOnOverflow;
     step(dbk::run_union(bufs, f3, s));
     step(dbk::run_compact_noncore(core, ni, list, st, true, s));
     step(dbk::run_border(bufs, b3, s));
@@ -355,6 +406,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   stats->thr_hi = hi;
   stats->pairs_listed = (int64_t)hst.edges;
   stats->pair_overflow = (hst.status & dbk::kStatusEdgeOverflow) ? 1 : 0;
+  stats->filter_fallback = (hst.status & (dbk::kStatusRange | dbk::kStatusBandOverflow)) ? 1 : 0;
+  stats->thr_lo = mfma ? hst.thr[0] : lo;
+  stats->thr_hi = mfma ? hst.thr[1] : hi;
   stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
   return stats->status;
 }

@@ -17,17 +17,25 @@
 
 namespace dbk {
 
-constexpr unsigned kStatusNonFinite = 1u;     // an input coordinate is NaN or inf
-constexpr unsigned kStatusEdgeOverflow = 2u;  // the neighbour-pair list ran out of room
+constexpr unsigned kStatusNonFinite = 1u;      // an input coordinate is NaN or inf
+constexpr unsigned kStatusEdgeOverflow = 2u;   // the neighbour-pair list ran out of room
+constexpr unsigned kStatusBandOverflow = 4u;   // the matrix-core band list ran out of room
+constexpr unsigned kStatusRange = 8u;          // inputs outside the low-precision range
+
+constexpr int kPrecBf16 = 2;  // values of dbscan_opts.precision
+constexpr int kPrecFp16 = 3;
 
 // Per-call device state (first 256 bytes of the workspace).
 struct DevState {
-  unsigned int status;           // kStatus* bits
-  unsigned int noncore;          // compaction cursor for non-core rows
-  unsigned long long band_pairs; // pairs re-evaluated in float64 (all passes)
+  unsigned int status;             // kStatus* bits
+  unsigned int noncore;            // compaction cursor for non-core rows
+  unsigned long long band_pairs;   // pairs re-evaluated in float64 (all passes)
   unsigned long long core_points;
-  unsigned long long edges;      // pairs (i, j), j < i, appended to the pair list
-  unsigned long long reserved[4];
+  unsigned long long edges;        // pairs (i, j), j < i, appended to the pair list
+  unsigned long long band_list;    // pairs appended to the matrix-core band list
+  unsigned long long max_norm;     // bit pattern of max |x_i| (float64, >= 0)
+  float thr[2];                    // matrix-core filter thresholds (in, out)
+  unsigned long long reserved[2];
 };
 
 constexpr int kNoNeighbour = 0x7fffffff;
@@ -194,24 +202,37 @@ __device__ __forceinline__ void wq_drain_union(WaveQueue &q, int *parent, bool a
   }
 }
 
-// Append the queued pairs to the global pair list; past `cap` entries the
-// list is marked as overflowed and the pairs are dropped.
-__device__ __forceinline__ void wq_drain_list(WaveQueue &q, int2 *list, long long cap,
-                                              DevState *st, bool all) {
+// Append the queued pairs to a global list at *cursor; past `cap` entries the
+// pairs are dropped and `flag` is raised in the status word.
+__device__ __forceinline__ void wq_drain_to(WaveQueue &q, int2 *list, long long cap,
+                                            unsigned long long *cursor, unsigned *status,
+                                            unsigned flag, bool all) {
   while (q.count >= 64 || (all && q.count > 0)) {
     const int take = q.count < 64 ? q.count : 64;
     const int lane = lane_id();
     unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(&st->edges, (unsigned long long)take);
+    if (lane == 0) base = atomicAdd(cursor, (unsigned long long)take);
     base = __shfl(base, 0);
     if (lane < take) {
       const unsigned long long idx = base + (unsigned long long)lane;
       if (idx < (unsigned long long)cap) list[idx] = q.buf[lane];
     }
     if (lane == 0 && base + (unsigned long long)take > (unsigned long long)cap)
-      atomicOr(&st->status, kStatusEdgeOverflow);
+      atomicOr(status, flag);
     wq_pop(q, take);
   }
+}
+
+// Neighbour pairs (i, j), j < i, for the merge.
+__device__ __forceinline__ void wq_drain_list(WaveQueue &q, int2 *list, long long cap,
+                                              DevState *st, bool all) {
+  wq_drain_to(q, list, cap, &st->edges, &st->status, kStatusEdgeOverflow, all);
+}
+
+// Pairs the matrix-core filter could not decide.
+__device__ __forceinline__ void wq_drain_band(WaveQueue &q, int2 *list, long long cap,
+                                              DevState *st, bool all) {
+  wq_drain_to(q, list, cap, &st->band_list, &st->status, kStatusBandOverflow, all);
 }
 
 }  // namespace dbk

@@ -19,6 +19,7 @@ struct Buffers {
   const int *list;     // [n_pad] compacted non-core rows
   uint32_t *adjT;      // [n_pad/32][n_pad] bitmask adjacency (bitmask form only)
   int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
+  int2 *band;          // [band_cap] pairs the matrix-core filter leaves undecided
   DevState *st;
 };
 
@@ -29,7 +30,17 @@ struct SweepScalars {
   float lo, hi;        // float32 band: s <= lo in, s > hi out, else float64
   double eps2;
   long long edge_cap;  // capacity of the pair list (entries)
-  int flags;           // 1: run only if the pair list overflowed
+  int flags;           // kOnlyOnOverflow / kOnlyOnFilterFail
+};
+
+constexpr int kOnlyOnOverflow = 1;    // run only if the pair list overflowed
+constexpr int kOnlyOnFilterFail = 2;  // run only if the matrix-core filter gave up
+
+// Scalars of the matrix-core sweep.
+struct MfmaScalars {
+  int n, n_pad, d;
+  int nchunks, chunk;  // row split: chunk = 32-row tiles per chunk
+  long long pair_cap, band_cap;
 };
 
 int rows_per_wave(int d);
@@ -47,6 +58,17 @@ hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *co
 hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
+hipError_t run_filter_fallback(int *counts, int n, DevState *st, hipStream_t s);
+
+int mfma_k(int d);
+hipError_t run_mfma_prep(const float *pts, int n, int d, int n_pad, int prec, void *a_aug,
+                         void *b_aug, DevState *st, hipStream_t s);
+hipError_t run_mfma_thresholds(DevState *st, double eps2, int d, int prec, double band_rel,
+                               hipStream_t s);
+hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b,
+                          const MfmaScalars &sc, int prec, hipStream_t s);
+hipError_t run_recheck_band(const float *pts, int d, const Buffers &b, double eps2,
+                            long long band_cap, long long pair_cap, hipStream_t s);
 hipError_t run_union_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
                       const DevState *st, hipStream_t s);

@@ -15,12 +15,17 @@
 
 namespace dbk {
 
-constexpr int kOnlyOnOverflow = 1;
-
+// A fallback sweep runs only when the status word says its primary path
+// gave up (pair list overflow, or matrix-core filter out of range / band
+// list overflow).
 __device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevState *st) {
-  if (!(sc.flags & kOnlyOnOverflow)) return false;
-  return !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-           kStatusEdgeOverflow);
+  if (!sc.flags) return false;
+  const unsigned status =
+      __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if ((sc.flags & kOnlyOnOverflow) && (status & kStatusEdgeOverflow)) return false;
+  if ((sc.flags & kOnlyOnFilterFail) && (status & (kStatusRange | kStatusBandOverflow)))
+    return false;
+  return true;
 }
 
 // Lanes of the band (m & ~in) re-decided in float64; returns the exact mask.
@@ -38,6 +43,7 @@ __global__ __launch_bounds__(256) void k_count_small(const float *__restrict__ s
                                                      int2 *__restrict__ pairs,
                                                      DevState *__restrict__ st, SweepScalars sc) {
   __shared__ int2 qbuf[4][128];
+  if (skip_sweep(sc, st)) return;
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
   const int chunk = blockIdx.x % sc.nchunks;

@@ -236,3 +236,90 @@ def test_pair_list_overflow_falls_back(cap):
     half_edges = (int(ref[2].sum()) - w.n) // 2
     assert st["pairs_listed"] == half_edges
     assert st["pair_overflow"] == (1 if 0 < cap < half_edges else 0)
+
+
+# ------------------------------------------------------------ matrix cores
+PRECS = ("bf16", "fp16")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,d", [(1, 16), (70, 16), (1000, 16), (777, 32), (2050, 64), (513, 70)])
+def test_mfma_random(prec, n, d):
+    rng = np.random.default_rng(31 * n + d)
+    k = max(1, n // 60)
+    centres = rng.uniform(-5, 5, size=(k, d))
+    pts = (centres[rng.integers(0, k, size=n)] + 0.35 * rng.standard_normal((n, d))).astype(np.float32)
+    eps = float(0.4 * np.sqrt(d))
+    minpts = int(rng.integers(1, 8))
+    ref = orc.dbscan(pts, eps, minpts)
+    gpu = run(pts, eps, minpts, precision=prec, stats=True)
+    assert gpu[3]["precision_used"] == prec and gpu[3]["filter_fallback"] == 0
+    assert_same(gpu, ref, f"n={n} d={d} {prec}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mfma_integer_ties(prec):
+    """Integer coordinates: many pairs exactly at eps, all decided in float64."""
+    rng = np.random.default_rng(8)
+    base = rng.integers(-3, 4, size=(40, 16))
+    pts = np.concatenate([base + rng.integers(-1, 2, size=(40, 16)) * (rng.random((40, 16)) < 0.1)
+                          for _ in range(20)]).astype(np.float32)
+    for eps, minpts in ((1.0, 3), (np.sqrt(2.0), 5), (2.0, 8)):
+        gpu = run(pts, eps, minpts, precision=prec, stats=True)
+        assert_same(gpu, orc.dbscan(pts, eps, minpts), f"eps={eps}")
+        assert gpu[3]["pairs_rechecked"] > 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_mfma_band_overflow_and_range_fallback(prec):
+    w = wl.mix64d_300k(0, n=3000, eps_rule="q50")
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    gpu = run(w.points, w.eps, w.minpts, precision=prec, band_capacity=1, stats=True)
+    assert gpu[3]["filter_fallback"] == 1
+    assert_same(gpu, ref, "band overflow")
+    gpu = run(w.points, w.eps, w.minpts, precision=prec, pair_capacity=5, stats=True)
+    assert gpu[3]["pair_overflow"] == 1
+    assert_same(gpu, ref, "pair overflow")
+    if prec == "fp16":  # coordinates beyond the FP16 range of the filter
+        big = (w.points * 3000.0).astype(np.float32)
+        refb = c_oracle.dbscan(big, w.eps * 3000.0, w.minpts)
+        gpu = run(big, w.eps * 3000.0, w.minpts, precision=prec, stats=True)
+        assert gpu[3]["filter_fallback"] == 1
+        assert_same(gpu, refb, "range")
+
+
+@pytest.mark.parametrize("prec", PRECS + ("fp32",))
+def test_mix64d_scaled_parity(prec):
+    w = wl.mix64d_300k(0, n=8000, eps_rule="q50")
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    assert_same(run(w.points, w.eps, w.minpts, precision=prec), ref, prec)
+
+
+def test_mix64d_full_size_all_forms():
+    """n=300,000, d=64: the FP16 and BF16 filters and the plain float32 form
+    agree on every output at the literal eps (almost all noise) and at the
+    median core distance; sampled rows are exact against the oracle."""
+    for rule in ("literal", "q50"):
+        w = wl.mix64d_300k(0, eps_rule=rule)
+        outs = {p: run(w.points, w.eps, w.minpts, precision=p, stats=True)
+                for p in ("fp16", "bf16", "fp32")}
+        for p in ("bf16", "fp32"):
+            for x, y in zip(outs["fp16"][:3], outs[p][:3]):
+                np.testing.assert_array_equal(x, y, err_msg=f"{rule} fp16 vs {p}")
+        assert outs["fp16"][3]["filter_fallback"] == 0 and outs["bf16"][3]["filter_fallback"] == 0
+        rng = np.random.default_rng(2)
+        rows = np.sort(rng.choice(w.n, 24, replace=False))
+        gpu = outs["fp16"]
+        assert (gpu[2] >= 1).all()
+        if rule == "q50":
+            assert 0 < gpu[1].sum() < w.n
+        _sampled_checks(w, gpu, np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]]))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("d", [2, 3, 9])
+def test_mfma_small_d_on_request(prec, d):
+    rng = np.random.default_rng(d)
+    pts = rng.uniform(0, 4, size=(900, d)).astype(np.float32)
+    eps, minpts = 0.3 * np.sqrt(d), 4
+    assert_same(run(pts, eps, minpts, precision=prec), orc.dbscan(pts, eps, minpts), f"d={d}")
