@@ -92,6 +92,114 @@ def cpu_baseline(w, sample_n: int):
     }
 
 
+def _gen_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _gen_job(j):
+    from paper_1506_02226_amd import workloads
+    w = workloads.served_job(j)
+    return w.points, w.eps, w.minpts
+
+
+def serve_bench(args) -> int:
+    """Served form: seeded jobs (n log-uniform in [1e3, 2e5], d in
+    {2, 3, 16, 64}, 5-50 blobs, 5% noise, eps = 2% quantile of sampled core
+    distances, MinPts in {5, 10, 20}) on a dbscan_server.  A closed-loop run
+    (all jobs submitted at once) gives the saturation rate; an open-loop run
+    with Poisson arrivals at `--rate-frac` of it gives p50/p99 latency."""
+    import multiprocessing as mp
+    import threading
+    import torch
+    import paper_1506_02226_amd as pkg
+    from paper_1506_02226_amd import workloads
+
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1), initializer=_gen_init) as pool:
+        jobs = pool.map(_gen_job, range(args.jobs), chunksize=8)
+    t_gen = time.perf_counter() - t0
+    dev = torch.device("cuda:0")
+    xs = [torch.from_numpy(p).to(dev) for p, _, _ in jobs]
+    outs = [(torch.empty(x.shape[0], dtype=torch.int32, device=dev),
+             torch.empty(x.shape[0], dtype=torch.uint8, device=dev),
+             torch.empty(x.shape[0], dtype=torch.int32, device=dev)) for x in xs]
+    torch.cuda.synchronize()
+    n_tot = sum(int(x.shape[0]) for x in xs)
+    pairs_tot = sum(float(x.shape[0]) ** 2 for x in xs)
+
+    def run(arrivals):
+        with pkg.Server(max_slots=args.slots) as srv:
+            ids = [None] * len(jobs)
+            start = time.perf_counter()
+
+            def submitter():
+                for k, (x, (_, eps, mpts)) in enumerate(zip(xs, jobs)):
+                    if arrivals is not None:
+                        delay = arrivals[k] - (time.perf_counter() - start)
+                        if delay > 0:
+                            time.sleep(delay)
+                    ids[k] = srv.submit(x, eps, mpts, out=outs[k])
+
+            th = threading.Thread(target=submitter)
+            th.start()
+            th.join()
+            sts = [srv.wait(i, timeout=600) for i in ids]
+            stats = srv.stats()
+        lat = np.array([(s["t_done_ns"] - s["t_submit_ns"]) * 1e-6 for s in sts])
+        t_first = min(s["t_submit_ns"] for s in sts)
+        t_last = max(s["t_done_ns"] for s in sts)
+        span = (t_last - t_first) * 1e-9
+        bad = sum(1 for s in sts if s["state"] != pkg._lib.JOB_DONE or s["error"] != 0)
+        return {"span_s": span, "jobs_per_s": len(jobs) / span, "lat_ms": lat, "stats": stats,
+                "failed": bad, "fallback": sum(s["fallback"] for s in sts)}
+
+    closed = run(None)
+    rate = args.rate_frac * closed["jobs_per_s"]
+    arrivals = workloads.served_arrivals(len(jobs), rate, seed=0)
+    opened = run(arrivals)
+    # each result equals the same job run alone
+    rng = np.random.default_rng(0)
+    mismatches = 0
+    check = rng.choice(len(jobs), size=min(24, len(jobs)), replace=False)
+    for k in check:
+        _, eps, mpts = jobs[k]
+        alone = pkg.fit(xs[k], eps, mpts)
+        for a, b in zip(outs[k], alone):
+            mismatches += int(not torch.equal(a, b))
+    lat = opened["lat_ms"]
+    rec = {
+        "metric": "served jobs: p50/p99 latency, jobs/s",
+        "value": round(opened["jobs_per_s"], 2),
+        "unit": "jobs/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "f32/f16",
+        "data": "synthetic",
+        "config": {"workload": "served_jobs", "jobs": len(jobs), "slots": args.slots,
+                   "rate_jobs_per_s": round(rate, 2), "rate_frac_of_saturation": args.rate_frac},
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "mean_ms": round(float(lat.mean()), 3),
+        "saturation_jobs_per_s": round(closed["jobs_per_s"], 2),
+        "closed_loop_p50_ms": round(float(np.percentile(closed["lat_ms"], 50)), 3),
+        "closed_loop_p99_ms": round(float(np.percentile(closed["lat_ms"], 99)), 3),
+        "points_per_s": round(n_tot / opened["span_s"], 1),
+        "gpairs_per_s_saturated": round(pairs_tot / closed["span_s"] / 1e9, 3),
+        "epochs": int(opened["stats"]["epochs"]),
+        "peak_arena_gb": round(opened["stats"]["peak_bytes"] / 2**30, 3),
+        "failed": opened["failed"] + closed["failed"],
+        "standalone_fallbacks": opened["fallback"],
+        "alone_vs_mix_mismatches": mismatches,
+        "generation_s": round(t_gen, 1),
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +210,10 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample", type=int, default=80_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="served form (continuous batching)")
+    ap.add_argument("--jobs", type=int, default=5000)
+    ap.add_argument("--slots", type=int, default=256)
+    ap.add_argument("--rate-frac", type=float, default=0.7)
     args = ap.parse_args(argv)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -110,6 +222,9 @@ def main(argv=None) -> int:
               f"WORLD_SIZE={world}); rows shard across GPUs only in the design notes.",
               file=sys.stderr)
         return 2
+
+    if args.serve:
+        return serve_bench(args)
 
     import torch
     import paper_1506_02226_amd as pkg

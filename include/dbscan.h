@@ -171,6 +171,94 @@ int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_
  */
 int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi);
 
+/* ------------------------------------------------------------------ serving
+ * A server keeps a device job table and runs the jobs of many callers in one
+ * persistent kernel, relaunched every epoch (a time slice of ~2 ms):
+ * submitted jobs wait in a FIFO until a slot is free and their device-memory
+ * footprint (the dbscan_fit workspace of the job) fits in the server's arena;
+ * admitted jobs' block-sized tasks interleave on the device, and jobs that
+ * arrive while others run are admitted at the next epoch.  Each job's outputs
+ * equal those of dbscan_fit on the same inputs.  All entry points are
+ * thread-safe.
+ */
+typedef struct dbscan_server dbscan_server;
+
+#define DBSCAN_JOB_QUEUED 0
+#define DBSCAN_JOB_RUNNING 1
+#define DBSCAN_JOB_DONE 2
+#define DBSCAN_JOB_FAILED 3
+
+typedef struct dbscan_job {
+  const float *points;   /* DEVICE [n*d] row-major float32 (same rules as dbscan_fit) */
+  int64_t n;
+  int32_t d;
+  int32_t minpts;
+  double eps;
+  int32_t *labels;       /* DEVICE outputs, as in dbscan_fit */
+  uint8_t *core;
+  int32_t *counts;
+  uint64_t tag;          /* caller's value, returned in the status */
+} dbscan_job;
+
+typedef struct dbscan_job_status {
+  int32_t state;         /* DBSCAN_JOB_* */
+  int32_t error;         /* DBSCAN_OK or the error of a failed job */
+  int64_t t_submit_ns;   /* host steady clock, ns */
+  int64_t t_admit_ns;
+  int64_t t_done_ns;     /* completion (device clock mapped to the host clock) */
+  uint64_t footprint;    /* device bytes held while running */
+  uint64_t tag;
+  int32_t fallback;      /* 1 if the job ran through the dbscan_fit path */
+  int32_t reserved;
+} dbscan_job_status;
+
+typedef struct dbscan_server_stats {
+  int64_t jobs_submitted, jobs_admitted, jobs_done;
+  int64_t queued, running;
+  int64_t epochs;
+  int64_t busy_ns;       /* host time spent in epochs */
+  int64_t points_done;
+  double pairs_done;     /* sum of n^2 over finished jobs */
+  uint64_t budget_bytes, arena_used, peak_bytes;
+} dbscan_server_stats;
+
+/*
+ * dbscan_server_create -- server on HIP device `device` with a device-memory
+ * arena of hbm_budget_bytes (0 = 80% of the free memory) and at most
+ * max_slots jobs running at once (1..4096).  *out (HOST) receives the handle.
+ * Errors: DBSCAN_E_INVAL, DBSCAN_E_NOMEM, DBSCAN_E_DEVICE.
+ */
+int dbscan_server_create(int device, uint64_t hbm_budget_bytes, int32_t max_slots,
+                         dbscan_server **out);
+
+/*
+ * dbscan_batch_submit -- queue one job (HOST struct, DEVICE buffers that must
+ * stay valid until the job is finished).  *job_id (HOST) receives its id.
+ * DBSCAN_E_INVAL for bad arguments, DBSCAN_E_NOMEM if the job's footprint
+ * exceeds the whole arena, DBSCAN_E_AGAIN if the queue is full.
+ */
+int dbscan_batch_submit(dbscan_server *s, const dbscan_job *job, uint64_t *job_id);
+
+/*
+ * dbscan_batch_poll -- status of a job (HOST out).  Returns DBSCAN_OK once the
+ * job is finished (state DONE or FAILED), DBSCAN_PENDING before, and
+ * DBSCAN_E_INVAL for an unknown id.
+ */
+int dbscan_batch_poll(dbscan_server *s, uint64_t job_id, dbscan_job_status *st);
+
+/* dbscan_batch_wait -- dbscan_batch_poll that blocks up to timeout_ns. */
+int dbscan_batch_wait(dbscan_server *s, uint64_t job_id, int64_t timeout_ns,
+                      dbscan_job_status *st);
+
+/* dbscan_server_get_stats -- counters of the server (HOST out). */
+int dbscan_server_get_stats(dbscan_server *s, dbscan_server_stats *out);
+
+/*
+ * dbscan_server_destroy -- finish every queued and running job, then release
+ * the server.  Returns DBSCAN_OK or the first device error the server met.
+ */
+int dbscan_server_destroy(dbscan_server *s);
+
 /* dbscan_strerror -- static description of a return code. */
 const char *dbscan_strerror(int code);
 

@@ -18,7 +18,7 @@ import ctypes
 
 from . import _lib
 
-__all__ = ["fit", "workspace_size", "version", "DbscanError"]
+__all__ = ["fit", "workspace_size", "version", "DbscanError", "Server"]
 
 DbscanError = _lib.DbscanError
 
@@ -92,3 +92,87 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
     if stats:
         return labels, core, counts, st.as_dict()
     return labels, core, counts
+
+
+class Server:
+    """Continuously batched DBSCAN jobs on one GPU (dbscan_server_* ABI).
+
+    ``submit`` queues a job on device tensors and returns its id; ``poll`` /
+    ``wait`` return the status dict once the job is finished (None while it
+    is pending).  Jobs are admitted by device-memory footprint and run
+    together in the server's persistent kernel.  The caller keeps the input
+    and output tensors alive until the job is finished (``submit`` also keeps
+    a reference)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, max_slots: int = 256):
+        self._L = _lib.load()
+        h = ctypes.c_void_p()
+        rc = self._L.dbscan_server_create(int(device), int(hbm_budget), int(max_slots),
+                                          ctypes.byref(h))
+        if rc != _lib.DBSCAN_OK:
+            raise DbscanError(rc, "dbscan_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, points, eps: float, minpts: int, out=None, tag: int = 0) -> int:
+        import torch
+        x = _check_points(points)
+        n, d = int(x.shape[0]), int(x.shape[1])
+        if out is None:
+            out = (torch.empty(n, dtype=torch.int32, device=x.device),
+                   torch.empty(n, dtype=torch.uint8, device=x.device),
+                   torch.empty(n, dtype=torch.int32, device=x.device))
+        labels, core, counts = out
+        job = _lib.Job(x.data_ptr(), n, d, int(minpts), float(eps), labels.data_ptr(),
+                       core.data_ptr(), counts.data_ptr(), int(tag))
+        jid = ctypes.c_uint64()
+        rc = self._L.dbscan_batch_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
+        if rc != _lib.DBSCAN_OK:
+            raise DbscanError(rc, "dbscan_batch_submit")
+        self._keep[int(jid.value)] = (x, out)
+        return int(jid.value)
+
+    def outputs(self, job_id: int):
+        return self._keep[job_id][1]
+
+    def poll(self, job_id: int):
+        st = _lib.JobStatus()
+        rc = self._L.dbscan_batch_poll(self._h, int(job_id), ctypes.byref(st))
+        if rc == _lib.DBSCAN_PENDING:
+            return None
+        if rc != _lib.DBSCAN_OK:
+            raise DbscanError(rc, "dbscan_batch_poll")
+        return st.as_dict()
+
+    def wait(self, job_id: int, timeout: float = 60.0):
+        st = _lib.JobStatus()
+        rc = self._L.dbscan_batch_wait(self._h, int(job_id), int(timeout * 1e9), ctypes.byref(st))
+        if rc == _lib.DBSCAN_PENDING:
+            return None
+        if rc != _lib.DBSCAN_OK:
+            raise DbscanError(rc, "dbscan_batch_wait")
+        return st.as_dict()
+
+    def release(self, job_id: int) -> None:
+        self._keep.pop(job_id, None)
+
+    def stats(self) -> dict:
+        st = _lib.ServerStats()
+        rc = self._L.dbscan_server_get_stats(self._h, ctypes.byref(st))
+        if rc != _lib.DBSCAN_OK:
+            raise DbscanError(rc, "dbscan_server_get_stats")
+        return st.as_dict()
+
+    def close(self) -> None:
+        if self._h is not None:
+            rc = self._L.dbscan_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+            if rc != _lib.DBSCAN_OK:
+                raise DbscanError(rc, "dbscan_server_destroy")
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -34,7 +34,15 @@ EXPORTS = (
     "dbscan_strerror",
     "dbscan_version",
     "dbscan_fp32_band",
+    "dbscan_server_create",
+    "dbscan_batch_submit",
+    "dbscan_batch_poll",
+    "dbscan_batch_wait",
+    "dbscan_server_get_stats",
+    "dbscan_server_destroy",
 )
+
+JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
 
 
 class Opts(ctypes.Structure):
@@ -78,6 +86,57 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("points", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d", ctypes.c_int32),
+        ("minpts", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("labels", ctypes.c_void_p),
+        ("core", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p),
+        ("tag", ctypes.c_uint64),
+    ]
+
+
+class JobStatus(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_int32),
+        ("error", ctypes.c_int32),
+        ("t_submit_ns", ctypes.c_int64),
+        ("t_admit_ns", ctypes.c_int64),
+        ("t_done_ns", ctypes.c_int64),
+        ("footprint", ctypes.c_uint64),
+        ("tag", ctypes.c_uint64),
+        ("fallback", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("jobs_submitted", ctypes.c_int64),
+        ("jobs_admitted", ctypes.c_int64),
+        ("jobs_done", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("running", ctypes.c_int64),
+        ("epochs", ctypes.c_int64),
+        ("busy_ns", ctypes.c_int64),
+        ("points_done", ctypes.c_int64),
+        ("pairs_done", ctypes.c_double),
+        ("budget_bytes", ctypes.c_uint64),
+        ("arena_used", ctypes.c_uint64),
+        ("peak_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class DbscanError(RuntimeError):
     def __init__(self, code: int, where: str = ""):
         self.code = code
@@ -115,6 +174,19 @@ def load(path: str | None = None):
     L.dbscan_fp32_band.argtypes = [dbl, i32, ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float)]
     L.dbscan_fp32_band.restype = ctypes.c_int
+    sp = ctypes.c_void_p
+    L.dbscan_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, i32, ctypes.POINTER(sp)]
+    L.dbscan_server_create.restype = ctypes.c_int
+    L.dbscan_batch_submit.argtypes = [sp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+    L.dbscan_batch_submit.restype = ctypes.c_int
+    L.dbscan_batch_poll.argtypes = [sp, ctypes.c_uint64, ctypes.POINTER(JobStatus)]
+    L.dbscan_batch_poll.restype = ctypes.c_int
+    L.dbscan_batch_wait.argtypes = [sp, ctypes.c_uint64, i64, ctypes.POINTER(JobStatus)]
+    L.dbscan_batch_wait.restype = ctypes.c_int
+    L.dbscan_server_get_stats.argtypes = [sp, ctypes.POINTER(ServerStats)]
+    L.dbscan_server_get_stats.restype = ctypes.c_int
+    L.dbscan_server_destroy.argtypes = [sp]
+    L.dbscan_server_destroy.restype = ctypes.c_int
     if path is None:
         _lib = L
     return L

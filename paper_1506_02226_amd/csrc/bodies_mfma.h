@@ -1,0 +1,291 @@
+// Block-level bodies of the matrix-core filter (preparation, thresholds, tile
+// sweep, float64 band pass), shared by the standalone kernels and the
+// persistent serving loop.  The method and the bounds are described in
+// mfma_kernels.hip.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
+#include "dbscan_device.h"
+#include "dbscan_internal.h"
+
+namespace dbk {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+template <typename T> struct LowPrec;
+template <> struct LowPrec<__bf16> {
+  using vec8 = bf16x8;
+  static constexpr double u = 0x1p-8;        // unit roundoff (8-bit significand)
+  static constexpr double tiny = 0x1p-126;   // smallest normal
+  static constexpr float big = 0x1p100f;     // padding norm: any padded pair is far
+  static constexpr float maxval = 3.0e38f;
+  __device__ static vec8 zero() { return vec8{}; }
+  __device__ static f32x16 mfma(vec8 a, vec8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct LowPrec<_Float16> {
+  using vec8 = f16x8;
+  static constexpr double u = 0x1p-11;
+  static constexpr double tiny = 0x1p-14;
+  static constexpr float big = 60000.0f;
+  static constexpr float maxval = 30000.0f;  // |x| and the norm parts must stay in range
+  __device__ static vec8 zero() { return vec8{}; }
+  __device__ static f32x16 mfma(vec8 a, vec8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// ---------------------------------------------------------------- prepare
+// One thread per (padded) point: rounded coordinates, FP32 norm of the
+// rounded point split hi + lo, both augmented rows, and the float64 norm of
+// the original point for the bounds (max via an atomic on its bit pattern).
+template <typename T>
+__device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, int n, int d,
+                                               int n_pad, int K, T *__restrict__ a_aug,
+                                               T *__restrict__ b_aug, DevState *st, int bid) {
+  const int i = bid * 256 + (int)threadIdx.x;
+  if (i >= n_pad) return;
+  T *a = a_aug + (size_t)i * K;
+  T *b = b_aug + (size_t)i * K;
+  bool bad = false;
+  if (i < n) {
+    float nrm = 0.0f;
+    double nrm64 = 0.0;
+    for (int k = 0; k < d; ++k) {
+      const float x = pts[(size_t)i * d + k];
+      bad |= !__builtin_isfinite(x) || __builtin_fabsf(x) > LowPrec<T>::maxval;
+      const T xr = (T)x;
+      const float xf = (float)xr;
+      nrm = __builtin_fmaf(xf, xf, nrm);
+      nrm64 += (double)x * (double)x;
+      a[k] = xr;
+      b[k] = (T)(-2.0f * xf);
+    }
+    bad |= !(nrm <= LowPrec<T>::maxval);
+    const T hi = (T)nrm;
+    const T lo = (T)(nrm - (float)hi);
+    a[d] = hi;
+    a[d + 1] = lo;
+    a[d + 2] = (T)1.0f;
+    a[d + 3] = (T)1.0f;
+    b[d] = (T)1.0f;
+    b[d + 1] = (T)1.0f;
+    b[d + 2] = hi;
+    b[d + 3] = lo;
+    const double m = __builtin_sqrt(nrm64);
+    atomicMax(&st->max_norm, (unsigned long long)__double_as_longlong(m));
+  } else {
+    for (int k = 0; k < d; ++k) {
+      a[k] = (T)0.0f;
+      b[k] = (T)0.0f;
+    }
+    a[d] = (T)LowPrec<T>::big;
+    a[d + 1] = (T)0.0f;
+    a[d + 2] = (T)1.0f;
+    a[d + 3] = (T)1.0f;
+    b[d] = (T)1.0f;
+    b[d + 1] = (T)1.0f;
+    b[d + 2] = (T)LowPrec<T>::big;
+    b[d + 3] = (T)0.0f;
+  }
+  for (int k = d + 4; k < K; ++k) {
+    a[k] = (T)0.0f;
+    b[k] = (T)0.0f;
+  }
+  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusRange);
+}
+
+// ------------------------------------------------------------- thresholds
+// Neighbouring float32 values (finite x).
+__device__ __forceinline__ float next_down(float x) {
+  if (x == 0.0f) return -__uint_as_float(1u);
+  const unsigned b = __float_as_uint(x);
+  return __uint_as_float(x > 0.0f ? b - 1u : b + 1u);
+}
+__device__ __forceinline__ float next_up(float x) { return -next_down(-x); }
+
+// Bounds (all in float64, then rounded outward to float32):
+//   |x - x~| <= u |x| + sqrt(d) tiny per point, so |D - D~| <= Delta with
+//   Delta = 2 (u M + sqrt(d) tiny), M = max |x_i| (D = |x_i - x_j| exact,
+//   D~ the same for the rounded points);
+//   |s~ - D~^2| <= E = c (|x~_i|^2 + |x~_j|^2) with c covering the FP32 norm
+//   (gamma_d), its hi+lo split and the FP32 accumulation of the 2K-term
+//   contraction counted twice (the matrix core's internal order is not
+//   specified); |x~|^2 <= (M(1+u) + sqrt(d) tiny)^2;
+//   the float64 definition decides in when S <= eps2 (1 - 2 g64) and out when
+//   S >= eps2 (1 + 2 g64), g64 = (d+2) 2^-53.
+// In: s~ <= (eps_in - Delta)^2 - E.  Out: s~ > (eps_out + Delta)^2 + E.  The
+// band is then widened to at least |s - eps2| <= band_rel * eps2.
+template <typename T>
+__device__ __forceinline__ void mfma_thresholds_body(DevState *st, double eps2, int d, int K,
+                                                     double band_rel) {
+  const double u = LowPrec<T>::u, tiny = LowPrec<T>::tiny;
+  const double M = __longlong_as_double((long long)st->max_norm) * (1.0 + 1e-12);
+  const double sd = __builtin_sqrt((double)d) * (1.0 + 1e-12);
+  const double delta = 2.0 * (u * M + sd * tiny);
+  const double mt = M * (1.0 + u) + sd * tiny;
+  const double u32 = 0x1p-24;
+  const double g_norm = (d + 1) * u32 / (1.0 - (d + 1) * u32);
+  const double g_acc = (2.0 * K + 2) * u32 / (1.0 - (2.0 * K + 2) * u32);
+  const double split = 4.0 * u * u + 2.0 * u32;
+  const double c = g_norm + split + 2.01 * g_acc + 1e-12;
+  const double E = c * 2.0 * mt * mt + 4.0 * K * 0x1p-126;
+  const double g64 = (d + 2) * 0x1p-53;
+  const double eps_in = __builtin_sqrt(eps2 * (1.0 - 2.0 * g64)) * (1.0 - 1e-12);
+  const double eps_out = __builtin_sqrt(eps2 * (1.0 + 2.0 * g64)) * (1.0 + 1e-12);
+  double t_lo = (eps_in > delta) ? (eps_in - delta) * (eps_in - delta) - E : -1.0;
+  double t_hi = (eps_out + delta) * (eps_out + delta) + E;
+  t_lo = t_lo > 0.0 ? t_lo * (1.0 - 1e-12) : -1.0;
+  t_hi *= (1.0 + 1e-12);
+  const double s_lo = (1.0 - band_rel) * eps2, s_hi = (1.0 + band_rel) * eps2;
+  if (s_lo < t_lo) t_lo = s_lo;
+  if (s_hi > t_hi) t_hi = s_hi;
+  float lo = (float)t_lo, hi = (float)t_hi;
+  if (__builtin_isfinite(lo) && (double)lo > t_lo) lo = next_down(lo);
+  if (__builtin_isfinite(hi) && (double)hi < t_hi) hi = next_up(hi);
+  if (t_lo < 0.0) lo = -__builtin_inff();
+  st->thr[0] = lo;
+  st->thr[1] = hi;
+}
+
+// ------------------------------------------------------------ tile sweep
+constexpr int kMfmaColsPerWave = 64;                   // two 32-column tiles
+constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
+
+// LDS for one block of the tile sweep: two a-tiles and the pair/band queues.
+template <int KS>
+struct MfmaLds {
+  uint4 atile[2][2 * KS * 32];  // [buf][chunk*32 + row]: 16-byte chunks
+  int2 qbuf[4][2][128];
+};
+
+template <typename T, int KS>
+__device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
+                                                const T *__restrict__ b_aug,
+                                                int *__restrict__ counts,
+                                                int2 *__restrict__ pairs,
+                                                int2 *__restrict__ band,
+                                                DevState *__restrict__ st,
+                                                const MfmaScalars &sc, int bid,
+                                                MfmaLds<KS> &lds) {
+  using V = typename LowPrec<T>::vec8;
+  constexpr int K = KS * 16;
+  V (*atile)[2 * KS * 32] = reinterpret_cast<V (*)[2 * KS * 32]>(lds.atile);
+  int2 (*qbuf)[2][128] = lds.qbuf;
+  const int tid = threadIdx.x;
+  const int lane = lane_id();
+  const int w = wave_uniform(tid >> 6);
+  const int chunk = bid % sc.nchunks;
+  const int cgroup = bid / sc.nchunks;
+  const int col0 = cgroup * kMfmaColsPerGroup + w * kMfmaColsPerWave;
+  const int rt0 = chunk * sc.chunk;                    // first row tile
+  const int rt1 = min(rt0 + sc.chunk, sc.n_pad / 32);  // end row tile
+  const float t_lo = st->thr[0];
+  const float t_hi = st->thr[1];
+  const bool range_bad =
+      __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusRange;
+  if (range_bad || rt0 >= rt1) return;  // uniform over the work-group
+
+  // stationary b-fragments: lane l holds b[8*(l/32) + 16 s .. +7] of column l%32
+  V bfr[2][KS];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int j = col0 + c * 32 + (lane & 31);
+    const V *src = (const V *)(b_aug + (size_t)j * K);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) bfr[c][s] = src[2 * s + (lane >> 5)];
+  }
+  int cnt[2] = {0, 0};
+  WaveQueue qp{qbuf[w][0], 0};
+  WaveQueue qb{qbuf[w][1], 0};
+
+  // cooperative a-tile load: 32 rows x 2KS 16-byte chunks, stored chunk-major
+  // so that the 32 lanes reading one chunk of 32 rows hit consecutive banks
+  auto load_tile = [&](int rt, int buf) {
+    const V *src = (const V *)(a_aug + (size_t)rt * 32 * K);
+    for (int e = tid; e < 32 * 2 * KS; e += 256) {
+      const int row = e / (2 * KS), ch = e - row * (2 * KS);
+      atile[buf][ch * 32 + row] = src[e];
+    }
+  };
+  load_tile(rt0, 0);
+  __syncthreads();
+  for (int rt = rt0; rt < rt1; ++rt) {
+    const int buf = (rt - rt0) & 1;
+    if (rt + 1 < rt1) load_tile(rt + 1, buf ^ 1);
+    V afr[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(2 * s + (lane >> 5)) * 32 + (lane & 31)];
+    const int row_base = rt * 32 + 4 * (lane >> 5);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) acc = LowPrec<T>::mfma(afr[s], bfr[c][s], acc);
+      const int j = col0 + c * 32 + (lane & 31);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const float v = acc[r];
+        if (__ballot(v <= t_hi) != 0ull) {
+          const int i = row_base + 8 * (r >> 2) + (r & 3);
+          const bool valid = i < sc.n && j < sc.n;
+          const bool in = valid && v <= t_lo;
+          const bool amb = valid && !(v <= t_lo) && v <= t_hi;
+          cnt[c] += in ? 1 : 0;
+          wq_push(qp, in && i > j, i, j);
+          wq_drain_list(qp, pairs, sc.pair_cap, st, false);
+          wq_push(qb, amb, i, j);
+          wq_drain_band(qb, band, sc.band_cap, st, false);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  wq_drain_list(qp, pairs, sc.pair_cap, st, true);
+  wq_drain_band(qb, band, sc.band_cap, st, true);
+  // lanes l and l+32 hold the same column
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int tot = cnt[c] + __shfl_xor(cnt[c], 32);
+    const int j = col0 + c * 32 + lane;
+    if (lane < 32 && j < sc.n) atomicAdd(counts + j, tot);
+  }
+}
+
+// ------------------------------------------------------- float64 band pass
+// Each queued pair (i, j) is decided with the definition's arithmetic on the
+// FP32 inputs; "in" adds to the count of column j (the tile sweep counts
+// column j over all rows i) and i > j pairs go to the pair list.  This block
+// handles band entries [e_begin, e_end); `qbuf` is [4][128] pairs of LDS.
+__device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts, int d,
+                                                   const int2 *__restrict__ band,
+                                                   int *__restrict__ counts,
+                                                   int2 *__restrict__ pairs,
+                                                   DevState *__restrict__ st, double eps2,
+                                                   long long pair_cap,
+                                                   unsigned long long e_begin,
+                                                   unsigned long long e_end,
+                                                   int2 (*qbuf)[128]) {
+  const int w = wave_uniform(threadIdx.x >> 6);
+  WaveQueue qp{qbuf[w], 0};
+  for (unsigned long long e0 = e_begin + 64ull * w; e0 < e_end; e0 += 256) {
+    const unsigned long long e = e0 + (unsigned long long)lane_id();
+    bool in = false;
+    int2 pr = make_int2(0, 0);
+    if (e < e_end) {
+      pr = band[e];
+      in = exact_within_mem(pts + (size_t)pr.x * d, 1, pts + (size_t)pr.y * d, 1, d, eps2);
+      if (in) atomicAdd(counts + pr.y, 1);
+    }
+    wq_push(qp, in && pr.x > pr.y, pr.x, pr.y);
+    wq_drain_list(qp, pairs, pair_cap, st, false);
+  }
+  wq_drain_list(qp, pairs, pair_cap, st, true);
+}
+
+}  // namespace dbk

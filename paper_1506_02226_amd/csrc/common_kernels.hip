@@ -4,6 +4,7 @@
 // the neighbour-pair list, and canonical labels.
 #include "dbscan_device.h"
 #include "dbscan_internal.h"
+#include "bodies_common.h"
 
 namespace dbk {
 
@@ -22,48 +23,17 @@ __global__ void k_reset_state(DevState *st) {
   }
 }
 
-// soa[k][i] = points[i][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n.
-// Also clears counts, parent = identity, jstar = none; flags non-finite input.
 __global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, int d_pad,
                         float *__restrict__ soa, int *__restrict__ counts,
                         int *__restrict__ parent, int *__restrict__ jstar, DevState *st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;
-  bool bad = false;
-  const float qnan = __builtin_nanf("");
-  for (int k = 0; k < d_pad; ++k) {
-    float v;
-    if (i < n) {
-      v = (k < d) ? pts[(size_t)i * d + k] : 0.0f;
-      bad |= !__builtin_isfinite(v);
-    } else {
-      v = qnan;
-    }
-    soa[(size_t)k * n_pad + i] = v;
-  }
-  if (i < n) {
-    counts[i] = 0;
-    parent[i] = i;
-    jstar[i] = kNoNeighbour;
-  }
-  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNonFinite);
+  stage_body(pts, n, d, n_pad, d_pad, soa, counts, parent, jstar, st, blockIdx.x);
 }
 
 // ------------------------------------------------------------- core flags
 __global__ void k_core(const int *__restrict__ counts, int n, int n_pad, int minpts,
                        uint8_t *__restrict__ core, uint32_t *__restrict__ corebits,
                        DevState *st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_pad) return;  // n_pad is a multiple of 64: whole waves
-  const bool c = i < n && counts[i] >= minpts;
-  if (i < n) core[i] = c ? 1 : 0;
-  const uint64_t m = __ballot(c);
-  const int lane = lane_id();
-  if (lane == 0) {
-    corebits[i >> 5] = (uint32_t)m;
-    corebits[(i >> 5) + 1] = (uint32_t)(m >> 32);
-    if (m) atomicAdd(&st->core_points, (unsigned long long)__popcll(m));
-  }
+  core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x);
 }
 
 // Non-core rows into a list (any order) for the border pass that repeats the
@@ -86,10 +56,7 @@ __global__ void k_compact_noncore(const uint8_t *__restrict__ core, int n, int *
 }
 
 // --------------------------------------------- merge + border from the list
-// Every neighbour pair (a, b), b < a, found by step 1: core-core pairs are
-// joined in the union-find; a non-core end takes the smaller index of its
-// core neighbours (atomicMin), which after all pairs is its lowest-index core
-// neighbour.  Skipped when the list overflowed.
+// Skipped when the list overflowed (the repeated sweeps take over).
 __global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pairs,
                                                     const uint32_t *__restrict__ corebits,
                                                     int *__restrict__ parent,
@@ -100,36 +67,16 @@ __global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pai
   unsigned long long total =
       __hip_atomic_load(&st->edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (total > (unsigned long long)cap) total = (unsigned long long)cap;
-  const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-  for (unsigned long long e = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
-       e < total; e += stride) {
-    const int2 pr = pairs[e];
-    const bool ca = (corebits[pr.x >> 5] >> (pr.x & 31)) & 1u;
-    const bool cb = (corebits[pr.y >> 5] >> (pr.y & 31)) & 1u;
-    if (ca && cb)
-      uf_union(parent, pr.x, pr.y);
-    else if (ca)
-      atomicMin(jstar + pr.y, pr.x);
-    else if (cb)
-      atomicMin(jstar + pr.x, pr.y);
-  }
+  const unsigned long long per = (total + gridDim.x - 1) / gridDim.x;
+  const unsigned long long b = (unsigned long long)blockIdx.x * per;
+  const unsigned long long e = b + per < total ? b + per : total;
+  merge_pairs_range(pairs, corebits, parent, jstar, b, e);
 }
 
 // ------------------------------------------------------------------ labels
 __global__ void k_labels(int n, const uint8_t *__restrict__ core, const int *__restrict__ jstar,
                          int *__restrict__ parent, int *__restrict__ labels, const DevState *st) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (st->status & kStatusNonFinite) {
-    labels[i] = -2;
-    return;
-  }
-  if (core[i]) {
-    labels[i] = uf_find(parent, i);
-  } else {
-    const int j = jstar[i];
-    labels[i] = (j == kNoNeighbour) ? -1 : uf_find(parent, j);
-  }
+  labels_body(n, core, jstar, parent, labels, st, blockIdx.x);
 }
 
 // ----------------------------------------------------- filter fallback

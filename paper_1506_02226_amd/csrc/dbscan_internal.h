@@ -17,7 +17,7 @@ struct Buffers {
   int *parent;         // [n_pad] union-find forest
   int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
   const int *list;     // [n_pad] compacted non-core rows
-  uint32_t *adjT;      // [n_pad/32][n_pad] bitmask adjacency (bitmask form only)
+  void *adjT;          // [n_pad/16][n_pad] uint16 bitmask adjacency (bitmask form only)
   int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
   int2 *band;          // [band_cap] pairs the matrix-core filter leaves undecided
   DevState *st;

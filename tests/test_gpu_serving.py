@@ -1,0 +1,128 @@
+"""GPU tests of the served form: jobs of uneven n, d, eps and MinPts run
+together in the persistent loop; each result equals the same job run alone
+(dbscan_fit) and the CPU oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1506_02226_amd as pkg
+from oracle import c_oracle, dbscan_oracle as orc
+from paper_1506_02226_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to("cuda:0")
+
+
+def _host(out):
+    lab, core, cnt = (t.cpu().numpy() for t in out)
+    return lab, core.astype(bool), cnt
+
+
+def _mixed_jobs(count, seed, n_max=6000):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for j in range(count):
+        n = int(np.exp(rng.uniform(np.log(200), np.log(n_max))))
+        d = int(rng.choice([2, 3, 16, 64]))
+        k = int(rng.integers(3, 12))
+        minpts = int(rng.choice([5, 10, 20]))
+        pts = wl.isotropic_blobs(rng, n, d, k, 40.0, 0.05, 0.2, 1.0)
+        eps = wl.core_distance_quantile(pts, minpts, 0.3, 128, rng)
+        jobs.append((pts, eps, minpts))
+    return jobs
+
+
+def test_served_mix_equals_alone_and_oracle():
+    jobs = _mixed_jobs(24, seed=5)
+    xs = [_gpu(p) for p, _, _ in jobs]
+    with pkg.Server(max_slots=64) as srv:
+        ids = [srv.submit(x, eps, mp) for x, (_, eps, mp) in zip(xs, jobs)]
+        sts = [srv.wait(i, timeout=120) for i in ids]
+        stats = srv.stats()
+        torch.cuda.synchronize()
+        mixed = [_host(srv.outputs(i)) for i in ids]
+    assert all(s is not None and s["state"] == pkg._lib.JOB_DONE and s["error"] == 0 for s in sts)
+    assert stats["jobs_done"] == len(jobs) and stats["epochs"] >= 1
+    assert any(s["fallback"] == 0 for s in sts)
+    for (pts, eps, mp), x, got, st in zip(jobs, xs, mixed, sts):
+        alone = pkg.fit(x, eps, mp)
+        torch.cuda.synchronize()
+        alone = _host(alone)
+        for a, b in zip(got, alone):
+            np.testing.assert_array_equal(a, b)
+        ref = c_oracle.dbscan(pts, eps, mp)
+        np.testing.assert_array_equal(got[2], ref[2])
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[0], ref[0])
+        assert st["t_submit_ns"] <= st["t_admit_ns"] <= st["t_done_ns"]
+
+
+def test_served_admission_by_footprint():
+    """A budget that holds about two jobs at a time: every job still runs,
+    and the arena never holds more than the budget."""
+    jobs = _mixed_jobs(10, seed=9, n_max=3000)
+    budget = 48 << 20
+    with pkg.Server(hbm_budget=budget, max_slots=8) as srv:
+        ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in jobs]
+        sts = [srv.wait(i, timeout=120) for i in ids]
+        stats = srv.stats()
+        outs = [_host(srv.outputs(i)) for i in ids]
+    assert all(s["state"] == pkg._lib.JOB_DONE for s in sts)
+    assert stats["peak_bytes"] <= budget
+    assert max(s["footprint"] for s in sts) <= budget
+    for (pts, eps, mp), got in zip(jobs, outs):
+        ref = orc.dbscan(pts, eps, mp)
+        np.testing.assert_array_equal(got[0], ref[0])
+
+
+def test_served_rejects_and_fallbacks():
+    rng = np.random.default_rng(3)
+    with pkg.Server(hbm_budget=8 << 20, max_slots=4) as srv:
+        # a job whose footprint exceeds the whole arena
+        big = _gpu(rng.uniform(0, 1, size=(200_000, 2)))
+        with pytest.raises(pkg.DbscanError) as ei:
+            srv.submit(big, 0.01, 5)
+        assert ei.value.code == pkg._lib.DBSCAN_E_NOMEM
+        # d = 8 is not in the persistent loop: it runs through dbscan_fit
+        p8 = rng.uniform(0, 3, size=(700, 8)).astype(np.float32)
+        j8 = srv.submit(_gpu(p8), 1.0, 4)
+        # eps above the diameter: n^2/2 pairs overflow the pair list -> refit
+        pd = rng.uniform(0, 1, size=(500, 3)).astype(np.float32)
+        jd = srv.submit(_gpu(pd), 5.0, 3)
+        # non-finite input
+        pn = rng.uniform(0, 1, size=(300, 2)).astype(np.float32)
+        pn[7, 0] = np.inf
+        jn = srv.submit(_gpu(pn), 0.1, 3)
+        s8, sd, sn = srv.wait(j8), srv.wait(jd), srv.wait(jn)
+        o8, od, on = (_host(srv.outputs(j)) for j in (j8, jd, jn))
+    assert s8["fallback"] == 1 and sd["fallback"] == 1
+    for (p, eps, mp), got in (((p8, 1.0, 4), o8), ((pd, 5.0, 3), od)):
+        ref = orc.dbscan(p, eps, mp)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, np.asarray(b).astype(a.dtype))
+    assert sn["error"] == pkg._lib.DBSCAN_E_NONFINITE and (on[0] == -2).all()
+
+
+def test_served_jobs_arriving_while_others_run():
+    """Submit a large job, then small ones while it runs: the small ones are
+    admitted at epoch boundaries and finish before the large one."""
+    big = wl.blobs2d_200k(0, n=120_000)
+    small = _mixed_jobs(6, seed=12, n_max=2000)
+    with pkg.Server(max_slots=16) as srv:
+        jb = srv.submit(_gpu(big.points), big.eps, big.minpts)
+        ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in small]
+        sts = [srv.wait(i, timeout=120) for i in ids]
+        sb = srv.wait(jb, timeout=120)
+        outs = [_host(srv.outputs(i)) for i in ids]
+        ob = _host(srv.outputs(jb))
+    assert all(s["state"] == pkg._lib.JOB_DONE and s["fallback"] == 0 for s in sts + [sb])
+    assert max(s["t_done_ns"] for s in sts) < sb["t_done_ns"]
+    for (pts, eps, mp), got in zip(small, outs):
+        np.testing.assert_array_equal(got[0], orc.dbscan(pts, eps, mp)[0])
+    alone = _host(pkg.fit(_gpu(big.points), big.eps, big.minpts))
+    for a, b in zip(ob, alone):
+        np.testing.assert_array_equal(a, b)
