@@ -74,6 +74,26 @@ class HipEvents:
             self.lib.hipEventDestroy(e)
 
 
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    for rel, want in rec["sources_sha256"].items():
+        src = os.path.join(ROOT, rel)
+        if not os.path.exists(src):
+            return None
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != want:
+                return None
+    return rec["bytes_per_launch"]
+
+
 def cpu_baseline(w, sample_n: int):
     from oracle import c_oracle
     m = min(sample_n, w.n)
@@ -210,6 +230,8 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
     ap.add_argument("--cpu-sample", type=int, default=80_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration for profiles)")
     ap.add_argument("--serve", action="store_true", help="served form (continuous batching)")
     ap.add_argument("--jobs", type=int, default=5000)
     ap.add_argument("--slots", type=int, default=256)
@@ -244,6 +266,14 @@ def main(argv=None) -> int:
     # one checked call first: statistics (adjacency used, band pairs)
     kw = dict(adjacency=args.adjacency, precision=args.precision, out=out, workspace=ws)
     _, _, _, st = pkg.fit(x, w.eps, w.minpts, stats=True, **kw)
+
+    if args.copy_probe:
+        # 1 GiB: four times the last-level cache, so the copy streams from HBM
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     hip = HipEvents()
     ev = [hip.block(4) for _ in range(args.steps)]
@@ -304,6 +334,7 @@ def main(argv=None) -> int:
         "core_points": int(st["core_points"]),
         "roofline": roof,
     }
+    roof["traffic"] = measured_traffic(roof["kernel"], w.name)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
     print(json.dumps(rec), flush=True)

@@ -8,91 +8,126 @@
 namespace dbk {
 
 // ----------------------------------------------------- bitmask pass (d <= 4)
-// One wave owns 16 rows (the "goal points" of Section IV-A.3, in scalar
-// registers) and the 64 lanes hold 64 columns.  Per row, one compare gives
-// the 64-bit ballot of the row's neighbours among the columns (its popcount
-// is the row's count, on the scalar unit), and the same compare's result is
-// shifted into a per-lane 16-bit word with an add-with-carry (w = 2w + bit).
-// After the 16 rows, lane j holds the pairs (rows row0..row0+15, column j);
-// by symmetry that is row j's word for the columns row0..row0+15, stored at
-// adj[row0/16][j] -- a coalesced 128-byte store per wave.  Bit b of
-// adj[q][i] is the pair (i, 16q+b).  Padded rows (i >= n) are NaN, so their
-// words are written as zeros.
+// One wave takes 16 rows at a time (the "goal points" of Section IV-A.3, in
+// scalar registers) and the 64 lanes hold 64 columns.  Per row, one compare
+// gives the 64-bit ballot of the row's neighbours among the columns (its
+// popcount is the row's count, on the scalar unit), and the same compare's
+// result is shifted into a per-lane 16-bit word with an add-with-carry
+// (w = 2w + bit).  After the 16 rows, lane j holds the pairs (rows
+// row0..row0+15, column j); by symmetry that is row j's word for the columns
+// row0..row0+15, stored at adj[row0/16][j] -- a coalesced 128-byte store per
+// wave.  Bit b of adj[q][i] is the pair (i, 16q+b).  Padded rows and columns
+// (index >= n) are NaN, so their bits are zero.
+//
+// The relation is symmetric, so each unordered pair is tested once: a 16-row
+// block only visits the 64-column blocks from the one holding its own rows
+// onwards.  That stores adj[q][i] for every i >= 16q (all the lower triangle
+// the merge reads), and the counts come from both sides of each test: the
+// row side as ballot popcounts in scalar registers, the column side as the
+// popcount of the lane's word, summed per block in LDS and added to counts[]
+// once per block.  In the diagonal 64x64 block every row visits all 64
+// columns itself, so column sums are taken only off that block.
+//
+// A block owns sc.rgroup rows (4 waves, 16-row blocks dealt round-robin) and
+// the sc.chunk columns of one chunk; the grid is row groups x chunks, and a
+// block whose columns all lie before its rows has nothing to do.
+constexpr int kBitmaskMaxChunk = 4096;
+
 template <int D>
 __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
                                                  uint16_t *__restrict__ adj,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
   constexpr int R = 16;
+  __shared__ int colcnt[kBitmaskMaxChunk];
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
   const int chunk = blockIdx.x % sc.nchunks;
-  const int row0 = ((blockIdx.x / sc.nchunks) * 4 + w) * R;
-  if (row0 >= sc.n_pad) return;
+  const int g0 = (blockIdx.x / sc.nchunks) * sc.rgroup;
   const int c0 = chunk * sc.chunk;
   const int c1 = min(c0 + sc.chunk, sc.n_pad);
-  float xr[R][D];
+  if (g0 >= sc.n_pad || c1 <= g0) return;  // block-uniform
+  for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
+  __syncthreads();
+  const int g1 = min(g0 + sc.rgroup, sc.n_pad);
+  for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
+    const int diag = row0 & ~63;
+    const int cs = max(c0, diag);
+    if (cs >= c1) continue;  // wave-uniform
+    float xr[R][D];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-    for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
-  int cnt[R];
+      for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+    // two rows' counts per scalar register (a chunk has at most 4096 columns)
+    uint32_t cnt2[R / 2];
 #pragma unroll
-  for (int r = 0; r < R; ++r) cnt[r] = 0;
-  uint16_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
-  float xn[D];
+    for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
+    uint16_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
+    float xn[D];
 #pragma unroll
-  for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + c0 + lane];
-  for (int cb = c0; cb < c1; cb += 64) {
-    float xc[D];
+    for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+    for (int cb = cs; cb < c1; cb += 64) {
+      float xc[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) xc[k] = xn[k];
-    if (cb + 64 < c1) {
+      for (int k = 0; k < D; ++k) xc[k] = xn[k];
+      if (cb + 64 < c1) {
 #pragma unroll
-      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
-    }
-    uint32_t word = 0;
-#pragma unroll
-    for (int r = R - 1; r >= 0; --r) {
-      const float s = sq_dist32<D>(xr[r], xc);
-      uint64_t m, carry;
-      // m = ballot(s <= hi); word = 2*word + (this lane's bit of m)
-      asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
-          "v_addc_co_u32_e64 %0, %2, %0, %0, %1"
-          : "+v"(word), "=&s"(m), "=&s"(carry)
-          : "s"(sc.hi), "v"(s));
-      if (m != 0ull) {
-        const uint64_t lo_m = __ballot(s <= sc.lo);
-        uint64_t in = m;
-        if (lo_m != m) {
-          in = recheck_band<D>(m & ~lo_m, lo_m, xr[r], xc, sc.eps2, st);
-          word = (word & ~1u) | (uint32_t)((in >> lane) & 1ull);
-        }
-        cnt[r] += __popcll(in);
+        for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
       }
-    }
-    out[cb + lane] = (uint16_t)word;
-  }
-  int mine = 0;
+      uint32_t word = 0;
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (lane == r) mine = cnt[r];
-  const int row = row0 + lane;
-  if (lane < R && row < sc.n) {
-    if (sc.nchunks == 1)
-      counts[row] = mine;
-    else
-      atomicAdd(counts + row, mine);
+      for (int r = R - 1; r >= 0; --r) {
+        const float s = sq_dist32<D>(xr[r], xc);
+        uint64_t m, carry;
+        // m = ballot(s <= hi); word = 2*word + (this lane's bit of m)
+        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
+            "v_addc_co_u32_e64 %0, %2, %0, %0, %1"
+            : "+v"(word), "=&s"(m), "=&s"(carry)
+            : "s"(sc.hi), "v"(s));
+        if (m != 0ull) {
+          const uint64_t lo_m = __ballot(s <= sc.lo);
+          uint64_t in = m;
+          if (lo_m != m) {
+            in = recheck_band<D>(m & ~lo_m, lo_m, xr[r], xc, sc.eps2, st);
+            word = (word & ~1u) | (uint32_t)((in >> lane) & 1ull);
+          }
+          cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
+        }
+      }
+      out[cb + lane] = (uint16_t)word;
+      if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
+    }
+    int mine = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane == r) mine = (int)((cnt2[r >> 1] >> ((r & 1) * 16)) & 0xffffu);
+    const int row = row0 + lane;
+    if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < c1 - c0; t += 256) {
+    const int v = colcnt[t];
+    if (v != 0 && c0 + t < sc.n) atomicAdd(counts + c0 + t, v);
   }
 }
 
 // --------------------------------------------------- merge from the bitmask
-// One wave owns 64 rows; it walks the 16-column words q of a chunk up to the
-// diagonal.  Core rows queue their core neighbours j < i; the queue is
-// drained into the union-find 64 pairs at a time.
-__global__ __launch_bounds__(256) void k_union_bitmask(const uint16_t *__restrict__ adj,
+// Step 3 and the border points in one read of the lower triangle.  One wave
+// owns 64 rows i (lanes) and walks the 16-column words q of a chunk up to the
+// diagonal, so it sees every neighbour pair (i, j), j < i, once:
+//  * core i, core j: queued, and the queue is drained into the union-find 64
+//    pairs at a time;
+//  * core i, non-core j: i is a core neighbour of j (atomicMin on jstar[j]);
+//  * non-core i: its first core j in ascending order is its lowest core
+//    neighbour below it (atomicMin on jstar[i], then the row stops looking).
+// A non-core point's core neighbours above it are found by those rows, so
+// after the pass jstar[v] is the lowest-index core neighbour of every
+// non-core v.
+__global__ __launch_bounds__(256) void k_merge_bitmask(const uint16_t *__restrict__ adj,
                                                        const uint32_t *__restrict__ corebits,
                                                        int *__restrict__ parent,
+                                                       int *__restrict__ jstar,
                                                        SweepScalars p) {
   __shared__ int2 qbuf[4][128];
   const int lane = lane_id();
@@ -101,23 +136,49 @@ __global__ __launch_bounds__(256) void k_union_bitmask(const uint16_t *__restric
   const int rb = (blockIdx.x / p.nchunks) * 4 + w;
   if (rb * 64 >= p.n) return;
   const int i = rb * 64 + lane;
-  const bool is_core = i < p.n && ((corebits[i >> 5] >> (i & 31)) & 1u);
+  const bool valid = i < p.n;
+  const bool is_core = valid && ((corebits[i >> 5] >> (i & 31)) & 1u);
+  bool seek = valid && !is_core;
   const int qi = i >> 4;
   const int q0 = chunk * p.chunk;
   const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 16 + 1);  // lower triangle
-  if (q0 >= q1 || __ballot(is_core) == 0ull) return;
+  if (q0 >= q1) return;
   WaveQueue qu{qbuf[w], 0};
-  for (int q = q0; q < q1; ++q) {
-    const uint32_t cw = (corebits[q >> 1] >> ((q & 1) * 16)) & 0xffffu;
-    uint32_t word = (uint32_t)adj[(size_t)q * p.n_pad + i] & cw;
-    if (!is_core || q > qi) word = 0u;
-    else if (q == qi) word &= (1u << (i & 15)) - 1u;
-    while (__ballot(word != 0u) != 0ull) {
-      const bool has = word != 0u;
-      const int j = q * 16 + (has ? __builtin_ctz(word) : 0);
-      word &= word - 1u;
-      wq_push(qu, has, i, j);
-      wq_drain_union(qu, parent, false);
+  // kU words per lane are loaded before any is used, so that kU loads per
+  // wave are in flight (the loop is bound by load latency otherwise)
+  constexpr int kU = 8;
+  for (int qb = q0; qb < q1; qb += kU) {
+    uint32_t wv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = qb + u;
+      wv[u] = (q < q1) ? (uint32_t)adj[(size_t)q * p.n_pad + i] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = qb + u;
+      const uint32_t cw = (q < q1) ? ((corebits[q >> 1] >> ((q & 1) * 16)) & 0xffffu) : 0u;
+      uint32_t word = wv[u];
+      if (!valid || q > qi || q >= q1) word = 0u;
+      else if (q == qi) word &= (1u << (i & 15)) - 1u;
+      const uint32_t hit = word & cw;
+      if (seek && hit != 0u) {
+        atomicMin(jstar + i, q * 16 + __builtin_ctz(hit));
+        seek = false;
+      }
+      uint32_t bw = is_core ? (word & ~cw) : 0u;
+      while (bw != 0u) {
+        atomicMin(jstar + q * 16 + __builtin_ctz(bw), i);
+        bw &= bw - 1u;
+      }
+      uint32_t uw = is_core ? hit : 0u;
+      while (__ballot(uw != 0u) != 0ull) {
+        const bool has = uw != 0u;
+        const int j = q * 16 + (has ? __builtin_ctz(uw) : 0);
+        uw &= uw - 1u;
+        wq_push(qu, has, i, j);
+        wq_drain_union(qu, parent, false);
+      }
     }
   }
   wq_drain_union(qu, parent, true);
@@ -125,7 +186,9 @@ __global__ __launch_bounds__(256) void k_union_bitmask(const uint16_t *__restric
 
 // ------------------------------------------------------------ host launchers
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
-  const int groups = (sc.n_pad / 16 + 3) / 4;
+  if (sc.chunk % 64 != 0 || sc.chunk > kBitmaskMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0)
+    return hipErrorInvalidValue;
+  const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
   const dim3 grid(groups * sc.nchunks), block(256);
   switch (sc.d) {
     case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint16_t *)b.adjT, b.counts, b.st, sc); break;
@@ -137,10 +200,10 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
   return hipGetLastError();
 }
 
-hipError_t run_union_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
+hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
-  hipLaunchKernelGGL(k_union_bitmask, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                     (const uint16_t *)b.adjT, b.corebits, b.parent, sc);
+  hipLaunchKernelGGL(k_merge_bitmask, dim3(groups * sc.nchunks), dim3(256), 0, s,
+                     (const uint16_t *)b.adjT, b.corebits, b.parent, b.jstar, sc);
   return hipGetLastError();
 }
 

@@ -205,28 +205,56 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   WaveQueue qb{qbuf[w][1], 0};
 
   // cooperative a-tile load: 32 rows x 2KS 16-byte chunks, stored chunk-major
-  // so that the 32 lanes reading one chunk of 32 rows hit consecutive banks
-  auto load_tile = [&](int rt, int buf) {
+  // so that the 32 lanes reading one chunk of 32 rows hit consecutive banks.
+  // The next tile is fetched into registers before the current tile's
+  // matrix-core work and written to the other LDS buffer after it.
+  constexpr int kChunks = 32 * 2 * KS;
+  constexpr int kPer = (kChunks + 255) / 256;  // chunks per thread (1 or 2)
+  V pre[kPer];
+  auto fetch = [&](int rt) {
     const V *src = (const V *)(a_aug + (size_t)rt * 32 * K);
-    for (int e = tid; e < 32 * 2 * KS; e += 256) {
-      const int row = e / (2 * KS), ch = e - row * (2 * KS);
-      atile[buf][ch * 32 + row] = src[e];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      if (e < kChunks) pre[u] = src[e];
     }
   };
-  load_tile(rt0, 0);
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = tid + 256 * u;
+      if (e < kChunks) {
+        const int row = e / (2 * KS), ch = e - row * (2 * KS);
+        atile[buf][ch * 32 + row] = pre[u];
+      }
+    }
+  };
+  fetch(rt0);
+  stash(0);
   __syncthreads();
   for (int rt = rt0; rt < rt1; ++rt) {
     const int buf = (rt - rt0) & 1;
-    if (rt + 1 < rt1) load_tile(rt + 1, buf ^ 1);
+    const bool more = rt + 1 < rt1;
+    if (more) fetch(rt + 1);
     V afr[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(2 * s + (lane >> 5)) * 32 + (lane & 31)];
+    // two independent accumulation chains, interleaved
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      acc0 = LowPrec<T>::mfma(afr[s], bfr[0][s], acc0);
+      acc1 = LowPrec<T>::mfma(afr[s], bfr[1][s], acc1);
+    }
     const int row_base = rt * 32 + 4 * (lane >> 5);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      f32x16 acc = {};
+      const f32x16 acc = c ? acc1 : acc0;
+      // one test per tile: does any pair of this lane reach the band?
+      float mn = acc[0];
 #pragma unroll
-      for (int s = 0; s < KS; ++s) acc = LowPrec<T>::mfma(afr[s], bfr[c][s], acc);
+      for (int r = 1; r < 16; ++r) mn = __builtin_fminf(mn, acc[r]);
+      if (__ballot(mn <= t_hi) == 0ull) continue;
       const int j = col0 + c * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -244,6 +272,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
         }
       }
     }
+    if (more) stash(buf ^ 1);
     __syncthreads();
   }
   wq_drain_list(qp, pairs, sc.pair_cap, st, true);

@@ -84,4 +84,102 @@ __device__ __forceinline__ void count_small_body(const float *__restrict__ soa,
   }
 }
 
+// ------------------------------- step 1 + counts, d <= 4, one test per pair
+// The triangular form of count_small_body: a block owns sc.rgroup rows and
+// the sc.chunk columns of one chunk, and an R-row block of a wave only visits
+// the 64-column blocks from the one holding its own rows onwards, so each
+// unordered pair is tested once.  Counts come from both sides of a test: the
+// row side as ballot popcounts (scalar registers), the column side as a
+// per-lane tally (the add-with-carry of the ballot bit) summed per block in
+// `colcnt` (LDS, sc.chunk entries) and added to counts[] at the end.  In the
+// diagonal 64x64 block every row visits all 64 columns itself, so there the
+// column tally is not taken, and only pairs below the diagonal are listed.
+template <int D, int R, bool EMIT>
+__device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
+                                               int *__restrict__ counts,
+                                               int2 *__restrict__ pairs,
+                                               DevState *__restrict__ st,
+                                               const SweepScalars &sc, int bid,
+                                               int2 (*qbuf)[128], int *colcnt) {
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int chunk = bid % sc.nchunks;
+  const int g0 = (bid / sc.nchunks) * sc.rgroup;
+  const int c0 = chunk * sc.chunk;
+  const int c1 = min(c0 + sc.chunk, sc.n_pad);
+  if (g0 >= sc.n || c1 <= g0) return;  // block-uniform
+  for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
+  __syncthreads();
+  const int g1 = min(g0 + sc.rgroup, sc.n);
+  WaveQueue qu{qbuf[w], 0};
+  for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
+    const int diag = row0 & ~63;
+    const int cs = max(c0, diag);
+    if (cs >= c1) continue;  // wave-uniform
+    float xr[R][D];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+    int cnt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) cnt[r] = 0;
+    float xn[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+    for (int cb = cs; cb < c1; cb += 64) {
+      float xc[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) xc[k] = xn[k];
+      if (cb + 64 < c1) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+      }
+      const bool off = cb != diag;
+      uint32_t tally = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float s = sq_dist32<D>(xr[r], xc);
+        uint64_t m, carry;
+        // m = ballot(s <= hi); tally += this lane's bit of m
+        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
+            "v_addc_co_u32_e64 %0, %2, %0, 0, %1"
+            : "+v"(tally), "=&s"(m), "=&s"(carry)
+            : "s"(sc.hi), "v"(s));
+        if (m != 0ull) {
+          const uint64_t lo_m = __ballot(s <= sc.lo);
+          uint64_t in = m;
+          if (lo_m != m) {
+            in = recheck_band<D>(m & ~lo_m, lo_m, xr[r], xc, sc.eps2, st);
+            tally -= (uint32_t)(((m ^ in) >> lane) & 1ull);  // in is a subset of m
+          }
+          cnt[r] += __popcll(in);
+          if (EMIT) {
+            if (off) {
+              wq_push(qu, (in >> lane) & 1ull, cb + lane, row0 + r);
+            } else {
+              const uint64_t e = in & below_mask(row0 + r, cb);
+              if (e != 0ull) wq_push(qu, (e >> lane) & 1ull, row0 + r, cb + lane);
+            }
+            wq_drain_list(qu, pairs, sc.edge_cap, st, false);
+          }
+        }
+      }
+      if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
+    }
+    int mine = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane == r) mine = cnt[r];
+    const int row = row0 + lane;
+    if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
+  }
+  if (EMIT) wq_drain_list(qu, pairs, sc.edge_cap, st, true);
+  __syncthreads();
+  for (int t = threadIdx.x; t < c1 - c0; t += 256) {
+    const int v = colcnt[t];
+    if (v != 0 && c0 + t < sc.n) atomicAdd(counts + c0 + t, v);
+  }
+}
+
 }  // namespace dbk

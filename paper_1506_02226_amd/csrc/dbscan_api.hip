@@ -157,6 +157,51 @@ Chunks split(int64_t units, int64_t row_waves, int64_t bytes_per_unit, int64_t m
   return c;
 }
 
+// Tiles of a triangular sweep: `rgroup` rows x `chunk` columns per block
+// (both multiples of 64, chunk <= max_chunk).  Starts at 512 x max_chunk and
+// halves the rows (then the columns) until the upper triangle holds enough
+// blocks to fill the chip several times over.
+struct Tri {
+  int nchunks, chunk, rgroup;
+};
+
+Tri tri_split(int64_t n_pad, int max_chunk) {
+  int64_t rg = 512, ch = max_chunk;
+  auto blocks = [&]() {
+    const int64_t g = (n_pad + rg - 1) / rg, c = (n_pad + ch - 1) / ch;
+    return g * c / 2 + 1;
+  };
+  while (blocks() < 4096 && (rg > 64 || ch > 256)) {
+    if (rg > 64)
+      rg /= 2;
+    else
+      ch /= 2;
+  }
+  Tri t;
+  t.rgroup = (int)rg;
+  t.chunk = (int)ch;
+  t.nchunks = (int)((n_pad + ch - 1) / ch);
+  return t;
+}
+
+// Tiles of the step-1 sweep: triangular for d <= 4, column chunks otherwise.
+dbk::SweepScalars sweep_tiles(const dbk::SweepScalars &sc, int64_t n, int64_t npad, int d,
+                              int d_pad) {
+  dbk::SweepScalars t = sc;
+  if (d <= 4) {
+    const Tri tr = tri_split(npad, 4096);
+    t.nchunks = tr.nchunks;
+    t.chunk = tr.chunk;
+    t.rgroup = tr.rgroup;
+  } else {
+    const int R = dbk::rows_per_wave(d);
+    const Chunks c = split(npad / 64, (n + R - 1) / R, 64LL * d_pad * 4, 2);
+    t.nchunks = c.nchunks;
+    t.chunk = c.chunk * 64;
+  }
+  return t;
+}
+
 int hip_fail(hipError_t e, dbscan_stats *stats) {
   if (stats) {
     stats->status = DBSCAN_E_DEVICE;
@@ -310,26 +355,18 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     step(dbk::run_recheck_band(points, d, bufs, eps2, L.band_cap, L.edge_cap, s));
     // the float32 sweep redoes step 1 only if the filter gave up
     step(dbk::run_filter_fallback(counts, ni, st, s));
-    const int R = dbk::rows_per_wave(d);
-    const Chunks cf = split(npad / 64, (n + R - 1) / R, 64LL * L.d_pad * 4, 2);
-    dbk::SweepScalars f1 = sc;
-    f1.nchunks = cf.nchunks;
-    f1.chunk = cf.chunk * 64;
+    dbk::SweepScalars f1 = sweep_tiles(sc, n, npad, d, L.d_pad);
     f1.flags = dbk::kOnlyOnFilterFail;
     step(dbk::run_count(bufs, f1, false, s));
   } else if (bitmask) {
-    const Chunks c = split(npad / 64, npad / 16, 64LL * d * 4, 2);
+    const Tri t = tri_split(npad, 4096);
     dbk::SweepScalars b1 = sc;
-    b1.nchunks = c.nchunks;
-    b1.chunk = c.chunk * 64;
+    b1.nchunks = t.nchunks;
+    b1.chunk = t.chunk;
+    b1.rgroup = t.rgroup;
     step(dbk::run_bitmask(bufs, b1, s));
   } else {
-    const int R = dbk::rows_per_wave(d);
-    const Chunks c = split(npad / 64, (n + R - 1) / R, 64LL * L.d_pad * 4, 2);
-    dbk::SweepScalars c1 = sc;
-    c1.nchunks = c.nchunks;
-    c1.chunk = c.chunk * 64;
-    step(dbk::run_count(bufs, c1, use_pairs, s));
+    step(dbk::run_count(bufs, sweep_tiles(sc, n, npad, d, L.d_pad), use_pairs, s));
   }
   mark(1);
   // ---- step 2: core flags
@@ -350,9 +387,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     dbk::SweepScalars u3 = sc;
     u3.nchunks = c.nchunks;
     u3.chunk = c.chunk;
-    step(dbk::run_union_bitmask(bufs, u3, s));
-    step(dbk::run_compact_noncore(core, ni, list, st, false, s));
-    step(dbk::run_border(bufs, b3, s));
+    step(dbk::run_merge_bitmask(bufs, u3, s));  // union-find and border points
   } else if (use_pairs) {
     // pair list; the repeated sweeps run only if it overflowed
     step(dbk::run_merge_list(bufs, L.edge_cap, s));

@@ -31,6 +31,7 @@ struct SweepScalars {
   double eps2;
   long long edge_cap;  // capacity of the pair list (entries)
   int flags;           // kOnlyOnOverflow / kOnlyOnFilterFail
+  int rgroup;          // rows per block of the triangular sweeps (multiple of 64)
 };
 
 constexpr int kOnlyOnOverflow = 1;    // run only if the pair list overflowed
@@ -69,7 +70,7 @@ hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b
                           const MfmaScalars &sc, int prec, hipStream_t s);
 hipError_t run_recheck_band(const float *pts, int d, const Buffers &b, double eps2,
                             long long band_cap, long long pair_cap, hipStream_t s);
-hipError_t run_union_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
+hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
                       const DevState *st, hipStream_t s);
 

@@ -26,6 +26,8 @@ enum ServePhase {
 enum ServeState { kJobFree = 0, kJobActive = 1, kJobDone = 2, kJobFailed = 3 };
 
 constexpr int kServeSlice = 4096;  // pairs per task in the list phases
+constexpr int kServeTriChunk = 4096;  // columns per float32 step-1 task (LDS tallies)
+constexpr int kServeTriRows = 128;    // rows per float32 step-1 task
 
 // Read-only description of one admitted job (written by the host before an
 // epoch starts).
@@ -50,6 +52,7 @@ struct JobDesc {
   float lo, hi;      // float32 band (direct form)
   long long pair_cap, band_cap;
   int nchunks, chunk;  // step-1 split (columns for float32, 32-row tiles for matrix cores)
+  int rgroup;          // float32: rows per task of the triangular sweep
 };
 
 // Mutable scheduling state of one job slot.

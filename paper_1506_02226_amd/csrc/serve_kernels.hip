@@ -25,6 +25,10 @@ constexpr int kIdlePolls = 256;    // idle polls (~0.2 us each) before a block l
 union ServeLds {
   MfmaLds<5> m;
   int2 q[4][128];
+  struct {
+    int2 q[4][128];
+    int colcnt[kServeTriChunk];
+  } t;
 };
 
 __device__ __forceinline__ unsigned long long ld_acq(const unsigned long long *p) {
@@ -50,6 +54,7 @@ __device__ __forceinline__ SweepScalars plain_scalars(const JobDesc &jd) {
   sc.eps2 = jd.eps2;
   sc.edge_cap = jd.pair_cap;
   sc.flags = 0;
+  sc.rgroup = jd.rgroup;
   return sc;
 }
 
@@ -101,10 +106,10 @@ __device__ __forceinline__ void run_task(const JobDesc &jd, int phase, int idx, 
       } else {
         const SweepScalars sc = plain_scalars(jd);
         switch (jd.d) {
-          case 1: count_small_body<1, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.q); break;
-          case 2: count_small_body<2, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.q); break;
-          case 3: count_small_body<3, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.q); break;
-          default: count_small_body<4, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.q); break;
+          case 1: count_tri_body<1, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
+          case 2: count_tri_body<2, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
+          case 3: count_tri_body<3, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
+          default: count_tri_body<4, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
         }
       }
       break;

@@ -42,8 +42,8 @@ inline int64_t now_ns() {
 }
 inline uint64_t round_up(uint64_t v, uint64_t m) { return (v + m - 1) / m * m; }
 
-constexpr uint64_t kServePairsPerPoint = 32;
-constexpr uint64_t kServeBandPerPoint = 16;
+constexpr uint64_t kServePairsPerPoint = 128;  // as dbscan_fit's default
+constexpr uint64_t kServeBandPerPoint = 64;
 constexpr int kMaxQueue = 1 << 20;
 
 // First-fit allocator over [0, size) in 256-byte units.
@@ -323,12 +323,11 @@ void dbscan_server::loop() {
         jd.nchunks = (tiles + per - 1) / per;
         js.ntasks[dbk::kPhCount] = blocks256 * (unsigned)jd.nchunks;
       } else {
-        // 32 rows x a column chunk of <= 32768 per task
-        const int cblocks = L.n_pad / 64;
-        const int per = cblocks < 512 ? cblocks : 512;
-        jd.chunk = per * 64;
-        jd.nchunks = (cblocks + per - 1) / per;
-        const unsigned groups = (unsigned)(((jd.n + 7) / 8 + 3) / 4);
+        // triangular sweep: 128 rows x a column chunk of <= 4096 per task
+        jd.chunk = L.n_pad < dbk::kServeTriChunk ? L.n_pad : dbk::kServeTriChunk;
+        jd.nchunks = (L.n_pad + jd.chunk - 1) / jd.chunk;
+        jd.rgroup = dbk::kServeTriRows;
+        const unsigned groups = (unsigned)((jd.n + jd.rgroup - 1) / jd.rgroup);
         js.ntasks[dbk::kPhCount] = groups * (unsigned)jd.nchunks;
       }
       js.ntasks[dbk::kPhCore] = blocks256;

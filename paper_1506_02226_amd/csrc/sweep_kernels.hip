@@ -40,6 +40,20 @@ __global__ __launch_bounds__(256) void k_count_small(const float *__restrict__ s
   count_small_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf);
 }
 
+// Triangular form (each unordered pair tested once); LDS column tallies.
+constexpr int kTriMaxChunk = 4096;
+
+template <int D, int R, bool EMIT>
+__global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa,
+                                                   int *__restrict__ counts,
+                                                   int2 *__restrict__ pairs,
+                                                   DevState *__restrict__ st, SweepScalars sc) {
+  __shared__ int2 qbuf[4][128];
+  __shared__ int colcnt[kTriMaxChunk];
+  if (skip_sweep(sc, st)) return;
+  count_tri_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt);
+}
+
 // --------------------------------------- merge repeated on the fly, d <= 4
 // Core rows i queue their core neighbours j < i; the queue is drained into
 // the union-find 64 pairs at a time.
@@ -136,12 +150,19 @@ __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ 
     for (int r = 0; r < R; ++r) found[r] = kNoNeighbour;
     const int c0 = chunk * sc.chunk;
     const int c1 = min(c0 + sc.chunk, sc.n_pad);
+    float xn[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + c0 + lane];
     for (int cb = c0; cb < c1 && active != 0u; cb += 64) {
-      const uint64_t cw = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
-      if (cw == 0ull) continue;
       float xc[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xc[k] = soa[(size_t)k * sc.n_pad + cb + lane];
+      for (int k = 0; k < D; ++k) xc[k] = xn[k];
+      if (cb + 64 < c1) {  // next block's columns in flight during this one
+#pragma unroll
+        for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+      }
+      const uint64_t cw = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
+      if (cw == 0ull) continue;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         if (!((active >> r) & 1u)) continue;
@@ -352,12 +373,17 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
   const int R = rows_per_wave(sc.d);
   const int groups = ((sc.n + R - 1) / R + 3) / 4;
   const dim3 grid(groups * sc.nchunks), block(256);
+  if (sc.d > 4) return launch_lds<MODE_COUNT>(b, sc, (int)grid.x, s);
+  // d <= 4: the triangular sweep; sc.chunk / sc.rgroup give its tiles
+  if (sc.chunk % 64 != 0 || sc.chunk > kTriMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0)
+    return hipErrorInvalidValue;
+  const dim3 tgrid(((sc.n + sc.rgroup - 1) / sc.rgroup) * sc.nchunks);
 #define DBK_COUNT(D)                                                                          \
   if (emit_pairs)                                                                             \
-    hipLaunchKernelGGL((k_count_small<D, kRowsSmall, true>), grid, block, 0, s, b.soa,       \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true>), tgrid, block, 0, s, b.soa,        \
                        b.counts, b.pairs, b.st, sc);                                          \
   else                                                                                        \
-    hipLaunchKernelGGL((k_count_small<D, kRowsSmall, false>), grid, block, 0, s, b.soa,      \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, false>), tgrid, block, 0, s, b.soa,       \
                        b.counts, b.pairs, b.st, sc);                                          \
   break;
   switch (sc.d) {

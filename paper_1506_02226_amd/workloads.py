@@ -147,12 +147,16 @@ def aniso3d_2m(seed: int = 0, n: int = 2_000_000) -> Workload:
     return Workload("aniso3d_2m", pts, 0.4, 20, {"seed": seed, "blobs": k, "noise": 0.05})
 
 
-def _mix64d_points(seed: int, n: int, d: int = 64, k: int = 100) -> np.ndarray:
-    rng = np.random.default_rng(seed)
-    n_noise = int(round(0.02 * n))
+def mixture_blobs(
+    rng: np.random.Generator, n: int, d: int, k: int, noise_frac: float, radius: float = 10.0
+) -> np.ndarray:
+    """k unit-variance Gaussian components whose centres are random unit
+    vectors scaled by `radius`, plus uniform noise over the bounding box of
+    the component points."""
+    n_noise = int(round(noise_frac * n))
     n_blob = n - n_noise
     g = rng.standard_normal((k, d))
-    centres = 10.0 * g / np.linalg.norm(g, axis=1, keepdims=True)
+    centres = radius * g / np.linalg.norm(g, axis=1, keepdims=True)
     blob_pts = []
     for b, m in enumerate(blob_sizes(n_blob, k)):
         blob_pts.append(centres[b] + rng.standard_normal((m, d)))
@@ -160,6 +164,10 @@ def _mix64d_points(seed: int, n: int, d: int = 64, k: int = 100) -> np.ndarray:
     lo, hi = allb.min(axis=0), allb.max(axis=0)
     noise = rng.uniform(lo, hi, size=(n_noise, d))
     return _finish(rng, blob_pts, noise)
+
+
+def _mix64d_points(seed: int, n: int, d: int = 64, k: int = 100) -> np.ndarray:
+    return mixture_blobs(np.random.default_rng(seed), n, d, k, 0.02)
 
 
 def core_distance_quantile(
@@ -209,7 +217,10 @@ def served_job(j: int, eps_sample: int = 256) -> Workload:
     d = int(SERVED_D[rng.integers(0, len(SERVED_D))])
     k = int(rng.integers(5, 51))
     minpts = int(SERVED_MINPTS[rng.integers(0, len(SERVED_MINPTS))])
-    pts = isotropic_blobs(rng, n, d, k, 200.0, 0.05, 0.2, 1.0)
+    if d <= 3:  # the 2-D recipe: centres in [0, 200]^d, std in [0.2, 1]
+        pts = isotropic_blobs(rng, n, d, k, 200.0, 0.05, 0.2, 1.0)
+    else:  # the high-dimensional mixture recipe: centres at radius 10, std 1
+        pts = mixture_blobs(rng, n, d, k, 0.05)
     eps = core_distance_quantile(pts, minpts, 0.02, eps_sample, rng)
     return Workload(f"served_job_{j}", pts, eps, minpts, {"job": j, "blobs": k})
 

@@ -151,3 +151,21 @@ def test_band_sound_on_adversarial_pairs():
             assert exact > e2 * (1 - Fraction(1, 2 ** 50))
             checked += 1
     assert checked > 1000
+
+
+def test_server_entry_points_reject_bad_arguments():
+    """Serving entry points check their arguments on the host (no device)."""
+    L = _lib.load()
+    job = _lib.Job(0x1000, 100, 2, 5, 0.5, 0x2000, 0x3000, 0x4000, 0)
+    jid = ctypes.c_uint64()
+    st = _lib.JobStatus()
+    ss = _lib.ServerStats()
+    assert L.dbscan_batch_submit(None, ctypes.byref(job), ctypes.byref(jid)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_batch_poll(None, 1, ctypes.byref(st)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_batch_wait(None, 1, 0, ctypes.byref(st)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_server_get_stats(None, ctypes.byref(ss)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_server_destroy(None) == _lib.DBSCAN_E_INVAL
+    out = ctypes.c_void_p()
+    assert L.dbscan_server_create(0, 0, 0, ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_server_create(0, 0, 5000, ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_server_create(0, 0, 8, None) == _lib.DBSCAN_E_INVAL

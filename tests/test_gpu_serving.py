@@ -30,7 +30,10 @@ def _mixed_jobs(count, seed, n_max=6000):
         d = int(rng.choice([2, 3, 16, 64]))
         k = int(rng.integers(3, 12))
         minpts = int(rng.choice([5, 10, 20]))
-        pts = wl.isotropic_blobs(rng, n, d, k, 40.0, 0.05, 0.2, 1.0)
+        if d <= 3:
+            pts = wl.isotropic_blobs(rng, n, d, k, 40.0, 0.05, 0.2, 1.0)
+        else:
+            pts = wl.mixture_blobs(rng, n, d, k, 0.05)
         eps = wl.core_distance_quantile(pts, minpts, 0.3, 128, rng)
         jobs.append((pts, eps, minpts))
     return jobs
@@ -97,10 +100,15 @@ def test_served_rejects_and_fallbacks():
         pn = rng.uniform(0, 1, size=(300, 2)).astype(np.float32)
         pn[7, 0] = np.inf
         jn = srv.submit(_gpu(pn), 0.1, 3)
-        s8, sd, sn = srv.wait(j8), srv.wait(jd), srv.wait(jn)
-        o8, od, on = (_host(srv.outputs(j)) for j in (j8, jd, jn))
-    assert s8["fallback"] == 1 and sd["fallback"] == 1
-    for (p, eps, mp), got in (((p8, 1.0, 4), o8), ((pd, 5.0, 3), od)):
+        # squared norms beyond the half-precision range: the filter gives up
+        pw = rng.uniform(0, 200, size=(400, 16)).astype(np.float32)
+        pw[:200] = pw[0] + rng.normal(0, 1, size=(200, 16)).astype(np.float32)
+        jw = srv.submit(_gpu(pw), 4.0, 5)
+        s8, sd, sn, sw = srv.wait(j8), srv.wait(jd), srv.wait(jn), srv.wait(jw)
+        o8, od, on, ow = (_host(srv.outputs(j)) for j in (j8, jd, jn, jw))
+    assert s8["fallback"] == 1 and sd["fallback"] == 1 and sw["fallback"] == 1
+    assert sw["state"] == pkg._lib.JOB_DONE and sw["error"] == 0
+    for (p, eps, mp), got in (((p8, 1.0, 4), o8), ((pd, 5.0, 3), od), ((pw, 4.0, 5), ow)):
         ref = orc.dbscan(p, eps, mp)
         for a, b in zip(got, ref):
             np.testing.assert_array_equal(a, np.asarray(b).astype(a.dtype))
@@ -111,18 +119,21 @@ def test_served_jobs_arriving_while_others_run():
     """Submit a large job, then small ones while it runs: the small ones are
     admitted at epoch boundaries and finish before the large one."""
     big = wl.blobs2d_200k(0, n=120_000)
+    big_eps, big_minpts = 0.1, 10  # sparse enough for the served pair list
     small = _mixed_jobs(6, seed=12, n_max=2000)
     with pkg.Server(max_slots=16) as srv:
-        jb = srv.submit(_gpu(big.points), big.eps, big.minpts)
+        jb = srv.submit(_gpu(big.points), big_eps, big_minpts)
         ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in small]
         sts = [srv.wait(i, timeout=120) for i in ids]
         sb = srv.wait(jb, timeout=120)
         outs = [_host(srv.outputs(i)) for i in ids]
         ob = _host(srv.outputs(jb))
-    assert all(s["state"] == pkg._lib.JOB_DONE and s["fallback"] == 0 for s in sts + [sb])
+    states = [(s["state"], s["error"]) for s in sts + [sb]]
+    assert all(st == (pkg._lib.JOB_DONE, 0) for st in states), states
+    assert sb["fallback"] == 0
     assert max(s["t_done_ns"] for s in sts) < sb["t_done_ns"]
     for (pts, eps, mp), got in zip(small, outs):
         np.testing.assert_array_equal(got[0], orc.dbscan(pts, eps, mp)[0])
-    alone = _host(pkg.fit(_gpu(big.points), big.eps, big.minpts))
+    alone = _host(pkg.fit(_gpu(big.points), big_eps, big_minpts))
     for a, b in zip(ob, alone):
         np.testing.assert_array_equal(a, b)

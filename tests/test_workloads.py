@@ -40,3 +40,26 @@ def test_arrivals_poisson():
     t = wl.served_arrivals(2000, 100.0, seed=0)
     assert np.all(np.diff(t) > 0)
     assert abs(t[-1] / 2000 - 0.01) < 0.002
+
+
+def test_served_recipes_by_dimension():
+    """2-D/3-D jobs follow the 2-D blob recipe (box 200); 16-D/64-D jobs the
+    high-dimensional mixture recipe, whose squared norms stay inside the
+    half-precision range the matrix-core filter needs."""
+    seen = set()
+    for j in range(40):
+        w = wl.served_job(j, eps_sample=64)
+        x = w.points.astype(np.float64)
+        nrm2 = (x * x).sum(axis=1).max()
+        if w.d <= 3:
+            assert w.points.min() > -10 and w.points.max() < 210
+        else:
+            assert nrm2 < 30000.0
+        seen.add(w.d)
+    assert seen == {2, 3, 16, 64}
+
+
+def test_mixture_recipe_matches_mix64d():
+    a = wl._mix64d_points(0, 2000)
+    b = wl.mixture_blobs(np.random.default_rng(0), 2000, 64, 100, 0.02)
+    np.testing.assert_array_equal(a, b)
