@@ -96,10 +96,13 @@ typedef struct dbscan_opts {
                                  pairs awaiting the float64 pass (8 bytes each;
                                  0 = 64 per point).  If they do not fit, step 1
                                  is redone with the float32 direct form. */
-  void *events;               /* HOST, optional: hipEvent_t[4] created by the caller.
-                                 Recorded on `stream` (no wait) before the step-1
-                                 kernel and after steps 1, 2 and 3, so the caller
-                                 can time the kernels of a call it does not wait for. */
+  void *events;               /* HOST, optional: hipEvent_t[6] created by the caller.
+                                 Recorded on `stream` (no wait): [0] before step 1,
+                                 [1]-[3] after steps 1, 2 and 3, [4]/[5] just before
+                                 and after the step-1 sweep kernel alone (the
+                                 pair-test kernel, without staging or the float64
+                                 band pass), so the caller can time the kernels of
+                                 a call it does not wait for. */
 } dbscan_opts;
 
 typedef struct dbscan_stats {
@@ -122,6 +125,12 @@ typedef struct dbscan_stats {
   int32_t filter_fallback;/* 1 if the matrix-core filter gave up (inputs out of
                              its range or band_capacity exceeded) and step 1 was
                              redone in float32, else 0 */
+  float ms_sweep1;        /* the step-1 sweep kernel alone, device time */
+  int64_t sweep1_tests;   /* pair tests that kernel makes: about n^2/2 for the
+                             triangular float32 sweeps (d <= 4; each unordered
+                             pair once, both orders inside 64x64 diagonal
+                             blocks), n_pad^2 for the matrix-core tiles, about
+                             n*n_pad for d > 4 in float32 */
 } dbscan_stats;
 
 /*

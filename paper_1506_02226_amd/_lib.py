@@ -77,6 +77,8 @@ class Stats(ctypes.Structure):
         ("pairs_listed", ctypes.c_int64),
         ("pair_overflow", ctypes.c_int32),
         ("filter_fallback", ctypes.c_int32),
+        ("ms_sweep1", ctypes.c_float),
+        ("sweep1_tests", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -155,6 +155,7 @@ __device__ __forceinline__ void mfma_thresholds_body(DevState *st, double eps2, 
 
 // ------------------------------------------------------------ tile sweep
 constexpr int kMfmaColsPerWave = 64;                   // two 32-column tiles
+constexpr unsigned kBandBoth = 0x80000000u;            // band entry flag (row index bit 31)
 constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 
 // LDS for one block of the tile sweep: two a-tiles and the pair/band queues.
@@ -183,8 +184,14 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   const int chunk = bid % sc.nchunks;
   const int cgroup = bid / sc.nchunks;
   const int col0 = cgroup * kMfmaColsPerGroup + w * kMfmaColsPerWave;
-  const int rt0 = chunk * sc.chunk;                    // first row tile
-  const int rt1 = min(rt0 + sc.chunk, sc.n_pad / 32);  // end row tile
+  // Lower triangle only: row tiles from the group's own columns onwards.  The
+  // 8 row tiles that overlap the group's 256 columns (the diagonal zone) are
+  // computed in both orders and counted on the column side only; below them
+  // every pair (i > j) is tested once and counted on both sides.
+  const int diag_rt = cgroup * (kMfmaColsPerGroup / 32);
+  const int diag_end = diag_rt + kMfmaColsPerGroup / 32;
+  const int rt0 = max(chunk * sc.chunk, diag_rt);                  // first row tile
+  const int rt1 = min(chunk * sc.chunk + sc.chunk, sc.n_pad / 32);  // end row tile
   const float t_lo = st->thr[0];
   const float t_hi = st->thr[1];
   const bool range_bad =
@@ -247,6 +254,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
       acc1 = LowPrec<T>::mfma(afr[s], bfr[1][s], acc1);
     }
     const int row_base = rt * 32 + 4 * (lane >> 5);
+    const bool sym = rt >= diag_end;  // every row of the tile above every column
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const f32x16 acc = c ? acc1 : acc0;
@@ -265,9 +273,16 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
           const bool in = valid && v <= t_lo;
           const bool amb = valid && !(v <= t_lo) && v <= t_hi;
           cnt[c] += in ? 1 : 0;
+          if (sym) {
+            // row side: lanes 0-31 share one row, lanes 32-63 another
+            const uint64_t bm = __ballot(in);
+            const uint32_t half = (uint32_t)(bm >> (lane & 32));
+            if ((lane & 31) == 0 && half != 0u) atomicAdd(counts + i, __popc(half));
+          }
           wq_push(qp, in && i > j, i, j);
           wq_drain_list(qp, pairs, sc.pair_cap, st, false);
-          wq_push(qb, amb, i, j);
+          // band entries of the once-tested zone carry bit 31: both sides count
+          wq_push(qb, amb, sym ? (int)((unsigned)i | kBandBoth) : i, j);
           wq_drain_band(qb, band, sc.band_cap, st, false);
         }
       }
@@ -288,9 +303,10 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
 
 // ------------------------------------------------------- float64 band pass
 // Each queued pair (i, j) is decided with the definition's arithmetic on the
-// FP32 inputs; "in" adds to the count of column j (the tile sweep counts
-// column j over all rows i) and i > j pairs go to the pair list.  This block
-// handles band entries [e_begin, e_end); `qbuf` is [4][128] pairs of LDS.
+// FP32 inputs; "in" adds to the count of column j, and also of row i when the
+// entry carries kBandBoth (a pair the sweep tested in one order only), and
+// i > j pairs go to the pair list.  This block handles band entries
+// [e_begin, e_end); `qbuf` is [4][128] pairs of LDS.
 __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts, int d,
                                                    const int2 *__restrict__ band,
                                                    int *__restrict__ counts,
@@ -308,8 +324,13 @@ __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts
     int2 pr = make_int2(0, 0);
     if (e < e_end) {
       pr = band[e];
+      const bool both = ((unsigned)pr.x & kBandBoth) != 0u;
+      pr.x = (int)((unsigned)pr.x & ~kBandBoth);
       in = exact_within_mem(pts + (size_t)pr.x * d, 1, pts + (size_t)pr.y * d, 1, d, eps2);
-      if (in) atomicAdd(counts + pr.y, 1);
+      if (in) {
+        atomicAdd(counts + pr.y, 1);
+        if (both) atomicAdd(counts + pr.x, 1);
+      }
     }
     wq_push(qp, in && pr.x > pr.y, pr.x, pr.y);
     wq_drain_list(qp, pairs, pair_cap, st, false);

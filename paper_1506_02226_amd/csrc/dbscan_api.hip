@@ -202,6 +202,23 @@ dbk::SweepScalars sweep_tiles(const dbk::SweepScalars &sc, int64_t n, int64_t np
   return t;
 }
 
+// Pair tests made by the step-1 sweep kernel (its tiling, not n^2).
+int64_t sweep_tests(int64_t n, int64_t n_pad, int d, bool bitmask, bool mfma) {
+  if (mfma) {
+    // 256-column groups g test the row tiles from row 256 g on
+    const int64_t G = n_pad / 256;
+    return 65536 * G * (G + 1) / 2;
+  }
+  if (d > 4) return n * n_pad;
+  // 16-row (bitmask) or 8-row blocks from row 0 while below n_pad / n, each
+  // testing the columns from its own 64-column diagonal block to n_pad
+  const int64_t R = bitmask ? 16 : dbk::rows_per_wave(d);
+  const int64_t rows_end = bitmask ? n_pad : n;
+  int64_t t = 0;
+  for (int64_t row0 = 0; row0 < rows_end; row0 += R) t += R * (n_pad - (row0 & ~63LL));
+  return t;
+}
+
 int hip_fail(hipError_t e, dbscan_stats *stats) {
   if (stats) {
     stats->status = DBSCAN_E_DEVICE;
@@ -289,7 +306,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   band_fp32(eps2, d, &lo, &hi);
   const int ni = (int)n, npad = (int)L.n_pad;
 
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[6] = {};
   if (stats) {
     for (auto &e : ev) {
       hipError_t he = hipEventCreate(&e);
@@ -351,7 +368,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     ms.chunk = c.chunk;
     ms.pair_cap = L.edge_cap;
     ms.band_cap = L.band_cap;
+    mark(4);
     step(dbk::run_mfma_count(a_aug, b_aug, bufs, ms, L.precision, s));
+    mark(5);
     step(dbk::run_recheck_band(points, d, bufs, eps2, L.band_cap, L.edge_cap, s));
     // the float32 sweep redoes step 1 only if the filter gave up
     step(dbk::run_filter_fallback(counts, ni, st, s));
@@ -364,9 +383,14 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     b1.nchunks = t.nchunks;
     b1.chunk = t.chunk;
     b1.rgroup = t.rgroup;
+    mark(4);
     step(dbk::run_bitmask(bufs, b1, s));
+    mark(5);
   } else {
-    step(dbk::run_count(bufs, sweep_tiles(sc, n, npad, d, L.d_pad), use_pairs, s));
+    const dbk::SweepScalars c1 = sweep_tiles(sc, n, npad, d, L.d_pad);
+    mark(4);
+    step(dbk::run_count(bufs, c1, use_pairs, s));
+    mark(5);
   }
   mark(1);
   // ---- step 2: core flags
@@ -422,7 +446,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     for (auto &x : ev) (void)hipEventDestroy(x);
     return hip_fail(se, stats);
   }
-  float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+  float t01 = 0, t12 = 0, t23 = 0, t03 = 0, t45 = 0;
+  (void)hipEventElapsedTime(&t45, ev[4], ev[5]);
   (void)hipEventElapsedTime(&t01, ev[0], ev[1]);
   (void)hipEventElapsedTime(&t12, ev[1], ev[2]);
   (void)hipEventElapsedTime(&t23, ev[2], ev[3]);
@@ -444,6 +469,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   stats->filter_fallback = (hst.status & (dbk::kStatusRange | dbk::kStatusBandOverflow)) ? 1 : 0;
   stats->thr_lo = mfma ? hst.thr[0] : lo;
   stats->thr_hi = mfma ? hst.thr[1] : hi;
+  stats->ms_sweep1 = t45;
+  stats->sweep1_tests = sweep_tests(n, L.n_pad, d, L.adjacency == DBSCAN_ADJ_BITMASK, mfma);
   stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
   return stats->status;
 }

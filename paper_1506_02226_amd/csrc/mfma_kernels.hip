@@ -20,10 +20,13 @@
 // two 32-column MFMA tiles whose b-fragments stay in registers) and sweeps a
 // chunk of 32-row tiles whose a-fragments are staged in LDS (double buffered,
 // shared by the 4 waves).  Per tile pair a wave issues 2 x K/16 MFMAs
-// (v_mfma_f32_32x32x16_{bf16,f16}) and one compare per accumulator register;
-// the rare accumulator registers holding "in" or band pairs take a branch
-// that counts (per lane: lane l holds column l%32), queues neighbour pairs
-// i > j for the merge and queues band pairs for the float64 pass.
+// (v_mfma_f32_32x32x16_{bf16,f16}) and one min-reduction per accumulator;
+// the rare accumulators holding "in" or band pairs take a branch that counts
+// (per lane: lane l holds column l%32), queues neighbour pairs i > j for the
+// merge and queues band pairs for the float64 pass.  The relation is
+// symmetric, so a group sweeps only the row tiles from its own columns on:
+// below the 256x256 diagonal zone each pair is tested once and counted for
+// both ends (the row side from a ballot per accumulator register).
 #include "dbscan_device.h"
 #include "dbscan_internal.h"
 #include "bodies_mfma.h"

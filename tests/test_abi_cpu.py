@@ -169,3 +169,27 @@ def test_server_entry_points_reject_bad_arguments():
     assert L.dbscan_server_create(0, 0, 0, ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
     assert L.dbscan_server_create(0, 0, 5000, ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
     assert L.dbscan_server_create(0, 0, 8, None) == _lib.DBSCAN_E_INVAL
+
+
+@pytest.mark.parametrize("cname,pyname", [
+    ("dbscan_opts", "Opts"), ("dbscan_stats", "Stats"), ("dbscan_job", "Job"),
+    ("dbscan_job_status", "JobStatus"), ("dbscan_server_stats", "ServerStats")])
+def test_struct_layouts_match_header(cname, pyname, tmp_path):
+    """The ctypes mirrors have the header's size and field offsets (a plain C
+    program compiled against include/dbscan.h prints them)."""
+    import subprocess
+    cls = getattr(_lib, pyname)
+    fields = [f for f, _ in cls._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dbscan.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({cname}));']
+    lines += [f'  printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(cls)
+    assert out[1:] == [getattr(cls, f).offset for f in fields]

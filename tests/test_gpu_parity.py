@@ -57,6 +57,11 @@ def test_blobs2d_small(mode):
     assert_same(gpu, orc.dbscan(w.points, w.eps, w.minpts), mode)
     st = gpu[3]
     assert st["adjacency_used"] == mode and st["pairs_tested"] == w.n * w.n
+    # the triangular sweep tests each unordered pair once (both orders only
+    # inside the 64x64 diagonal blocks): between n(n+1)/2 and n(n+1)/2 + 64 n_pad
+    n_pad = -(-w.n // 256) * 256
+    assert w.n * (w.n + 1) // 2 <= st["sweep1_tests"] <= n_pad * (n_pad + 1) // 2 + 64 * n_pad
+    assert st["ms_sweep1"] > 0.0 and st["ms_sweep1"] <= st["ms_step1"] + 1e-3
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 1000, 4099])
