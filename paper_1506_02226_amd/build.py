@@ -21,6 +21,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-result",
+    # matrix-core accumulators in ordinary VGPRs: the filter's epilogue reads
+    # them directly instead of copying each out of the accumulation registers
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

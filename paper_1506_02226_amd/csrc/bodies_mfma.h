@@ -207,6 +207,9 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
 #pragma unroll
     for (int s = 0; s < KS; ++s) bfr[c][s] = src[2 * s + (lane >> 5)];
   }
+  // wait for them here: inside the loop only the next a-tile's loads are in
+  // flight, so the matrix-core work never waits on global memory
+  __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
   int cnt[2] = {0, 0};
   WaveQueue qp{qbuf[w][0], 0};
   WaveQueue qb{qbuf[w][1], 0};
@@ -223,7 +226,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + 256 * u;
-      if (e < kChunks) pre[u] = src[e];
+      pre[u] = src[e < kChunks ? e : kChunks - 1];  // unconditional: no branch
     }
   };
   auto stash = [&](int buf) {
