@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint16_t *__restric
   const int q0 = chunk * p.chunk;
   const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 16 + 1);  // lower triangle
   if (q0 >= q1) return;
-  WaveQueue qu{qbuf[w], 0};
+  WaveQueue qu{qbuf[w], 0, 64};
   // kU words per lane are loaded before any is used, so that kU loads per
   // wave are in flight (the loop is bound by load latency otherwise)
   constexpr int kU = 8;

@@ -158,12 +158,19 @@ constexpr int kMfmaColsPerWave = 64;                   // two 32-column tiles
 constexpr unsigned kBandBoth = 0x80000000u;            // band entry flag (row index bit 31)
 constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 
-// LDS for one block of the tile sweep: two a-tiles and the pair/band queues.
+// LDS for one block of the tile sweep: three a-tiles and the pair/band queues.
+// An a-tile is 32 rows of 2KS 16-byte chunks, row-major with a pitch of
+// 2KS+1 chunks: the pitch is odd, so the 16 rows that one pass of a 16-byte
+// read touches fall in 16 distinct bank groups (no conflicts), and the
+// writes, which follow the global row-major order, stay nearly conflict-free.
 template <int KS>
 struct MfmaLds {
-  uint4 atile[2][2 * KS * 32];  // [buf][chunk*32 + row]: 16-byte chunks
-  int2 qbuf[4][2][128];
+  static constexpr int kPitch = 2 * KS + 1;
+  uint4 atile[3][32 * kPitch];
+  int2 qbuf[4][2][kListQueue];
+  unsigned long long xfer[5];
 };
+
 
 template <typename T, int KS>
 __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
@@ -176,13 +183,22 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
                                                 MfmaLds<KS> &lds) {
   using V = typename LowPrec<T>::vec8;
   constexpr int K = KS * 16;
-  V (*atile)[2 * KS * 32] = reinterpret_cast<V (*)[2 * KS * 32]>(lds.atile);
-  int2 (*qbuf)[2][128] = lds.qbuf;
+  constexpr int kPitch = MfmaLds<KS>::kPitch;
+  V (*atile)[32 * kPitch] = reinterpret_cast<V (*)[32 * kPitch]>(lds.atile);
+  int2 (*qbuf)[2][kListQueue] = lds.qbuf;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = wave_uniform(tid >> 6);
-  const int chunk = bid % sc.nchunks;
-  const int cgroup = bid / sc.nchunks;
+  // item -> (column group, chunk); sc.chunk is a multiple of 8 row tiles
+  const int G = sc.n_pad / kMfmaColsPerGroup, kpc = sc.chunk / 8;
+  int lo = 0, hi = G - 1;
+  while (lo < hi) {  // last column group whose first item is <= bid
+    const int mid = (lo + hi + 1) >> 1;
+    if (mfma_items_before(mid, sc.nchunks, kpc) <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  const int cgroup = lo;
+  const int chunk = lo / kpc + (bid - (int)mfma_items_before(lo, sc.nchunks, kpc));
   const int col0 = cgroup * kMfmaColsPerGroup + w * kMfmaColsPerWave;
   // Lower triangle only: row tiles from the group's own columns onwards.  The
   // 8 row tiles that overlap the group's 256 columns (the diagonal zone) are
@@ -211,17 +227,19 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   // flight, so the matrix-core work never waits on global memory
   __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
   int cnt[2] = {0, 0};
-  WaveQueue qp{qbuf[w][0], 0};
-  WaveQueue qb{qbuf[w][1], 0};
+  WaveQueue qp{qbuf[w][0], 0, kListDrain};
+  WaveQueue qb{qbuf[w][1], 0, kListDrain};
 
-  // cooperative a-tile load: 32 rows x 2KS 16-byte chunks, stored chunk-major
-  // so that the 32 lanes reading one chunk of 32 rows hit consecutive banks.
-  // The next tile is fetched into registers before the current tile's
-  // matrix-core work and written to the other LDS buffer after it.
+  // cooperative a-tile load: 32 rows x 2KS 16-byte chunks (coalesced).
+  // Three LDS buffers: at the top of iteration t, tile t+1 (fetched into
+  // registers one iteration earlier) is written to buffer (t+1)%3 and tile t+2
+  // is fetched, then tile t is computed from buffer t%3; one barrier per
+  // iteration.  A global load has a whole iteration to land before its
+  // registers are written out, and no wait sits between the matrix-core work
+  // and the epilogue.
   constexpr int kChunks = 32 * 2 * KS;
   constexpr int kPer = (kChunks + 255) / 256;  // chunks per thread (1 or 2)
-  V pre[kPer];
-  auto fetch = [&](int rt) {
+  auto fetch = [&](V(&pre)[kPer], int rt) {
     const V *src = (const V *)(a_aug + (size_t)rt * 32 * K);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -229,26 +247,20 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
       pre[u] = src[e < kChunks ? e : kChunks - 1];  // unconditional: no branch
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](const V(&pre)[kPer], int buf) {
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + 256 * u;
       if (e < kChunks) {
         const int row = e / (2 * KS), ch = e - row * (2 * KS);
-        atile[buf][ch * 32 + row] = pre[u];
+        atile[buf][row * kPitch + ch] = pre[u];
       }
     }
   };
-  fetch(rt0);
-  stash(0);
-  __syncthreads();
-  for (int rt = rt0; rt < rt1; ++rt) {
-    const int buf = (rt - rt0) & 1;
-    const bool more = rt + 1 < rt1;
-    if (more) fetch(rt + 1);
+  auto tile = [&](int rt, int buf) {
     V afr[KS];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(2 * s + (lane >> 5)) * 32 + (lane & 31)];
+    for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(lane & 31) * kPitch + 2 * s + (lane >> 5)];
     // two independent accumulation chains, interleaved
     f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
@@ -290,11 +302,23 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
         }
       }
     }
-    if (more) stash(buf ^ 1);
+  };
+  V pre[kPer];
+  fetch(pre, rt0);
+  stash(pre, 0);
+  if (rt0 + 1 < rt1) fetch(pre, rt0 + 1);
+  __syncthreads();
+  int bcur = 0;
+  for (int rt = rt0; rt < rt1; ++rt) {
+    const int bnext = bcur == 2 ? 0 : bcur + 1;
+    if (rt + 1 < rt1) stash(pre, bnext);
+    if (rt + 2 < rt1) fetch(pre, rt + 2);
+    tile(rt, bcur);
     __syncthreads();
+    bcur = bnext;
   }
-  wq_drain_list(qp, pairs, sc.pair_cap, st, true);
-  wq_drain_band(qb, band, sc.band_cap, st, true);
+  wq_flush_block(qp, pairs, sc.pair_cap, &st->edges, &st->status, kStatusEdgeOverflow, lds.xfer);
+  wq_flush_block(qb, band, sc.band_cap, &st->band_list, &st->status, kStatusBandOverflow, lds.xfer);
   // lanes l and l+32 hold the same column
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -320,7 +344,7 @@ __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts
                                                    unsigned long long e_end,
                                                    int2 (*qbuf)[128]) {
   const int w = wave_uniform(threadIdx.x >> 6);
-  WaveQueue qp{qbuf[w], 0};
+  WaveQueue qp{qbuf[w], 0, 64};
   for (unsigned long long e0 = e_begin + 64ull * w; e0 < e_end; e0 += 256) {
     const unsigned long long e = e0 + (unsigned long long)lane_id();
     bool in = false;

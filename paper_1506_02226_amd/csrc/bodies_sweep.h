@@ -16,76 +16,8 @@ __device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const f
   return recheck_band<D>(m & ~in, in, a, b, eps2, st);
 }
 
-// ------------------------------------------------- step 1 + counts, d <= 4
-// One block = 4 waves x R rows over one column chunk; `qbuf` is the
-// block's LDS queue space ([4][128] pairs).
-template <int D, int R, bool EMIT>
-__device__ __forceinline__ void count_small_body(const float *__restrict__ soa,
-                                                 int *__restrict__ counts,
-                                                 int2 *__restrict__ pairs,
-                                                 DevState *__restrict__ st,
-                                                 const SweepScalars &sc, int bid,
-                                                 int2 (*qbuf)[128]) {
-  const int lane = lane_id();
-  const int w = wave_uniform(threadIdx.x >> 6);
-  const int chunk = bid % sc.nchunks;
-  const int row0 = ((bid / sc.nchunks) * 4 + w) * R;
-  if (row0 >= sc.n) return;
-  const int c0 = chunk * sc.chunk;
-  const int c1 = min(c0 + sc.chunk, sc.n_pad);
-  float xr[R][D];
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
-  int cnt[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) cnt[r] = 0;
-  WaveQueue qu{qbuf[w], 0};
-  float xn[D];
-#pragma unroll
-  for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + c0 + lane];
-  for (int cb = c0; cb < c1; cb += 64) {
-    float xc[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) xc[k] = xn[k];
-    if (cb + 64 < c1) {
-#pragma unroll
-      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const float s = sq_dist32<D>(xr[r], xc);
-      const uint64_t m = __ballot(s <= sc.hi);
-      if (m != 0ull) {
-        const uint64_t in = settle_band<D>(m, __ballot(s <= sc.lo), xr[r], xc, sc.eps2, st);
-        cnt[r] += __popcll(in);
-        if (EMIT) {
-          const uint64_t e = in & below_mask(row0 + r, cb);
-          if (e != 0ull) {
-            wq_push(qu, (e >> lane) & 1ull, row0 + r, cb + lane);
-            wq_drain_list(qu, pairs, sc.edge_cap, st, false);
-          }
-        }
-      }
-    }
-  }
-  if (EMIT) wq_drain_list(qu, pairs, sc.edge_cap, st, true);
-  int mine = 0;
-#pragma unroll
-  for (int r = 0; r < R; ++r)
-    if (lane == r) mine = cnt[r];
-  const int row = row0 + lane;
-  if (lane < R && row < sc.n) {
-    if (sc.nchunks == 1)
-      counts[row] = mine;
-    else
-      atomicAdd(counts + row, mine);
-  }
-}
-
 // ------------------------------- step 1 + counts, d <= 4, one test per pair
-// The triangular form of count_small_body: a block owns sc.rgroup rows and
+// A block owns sc.rgroup rows and
 // the sc.chunk columns of one chunk, and an R-row block of a wave only visits
 // the 64-column blocks from the one holding its own rows onwards, so each
 // unordered pair is tested once.  Counts come from both sides of a test: the
@@ -100,7 +32,8 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
                                                int2 *__restrict__ pairs,
                                                DevState *__restrict__ st,
                                                const SweepScalars &sc, int bid,
-                                               int2 (*qbuf)[128], int *colcnt) {
+                                               int2 (*qbuf)[kListQueue], int *colcnt,
+                                               unsigned long long *xfer) {
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
   const int chunk = bid % sc.nchunks;
@@ -111,7 +44,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
   __syncthreads();
   const int g1 = min(g0 + sc.rgroup, sc.n);
-  WaveQueue qu{qbuf[w], 0};
+  WaveQueue qu{qbuf[w], 0, kListDrain};
   for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
@@ -174,7 +107,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     const int row = row0 + lane;
     if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
   }
-  if (EMIT) wq_drain_list(qu, pairs, sc.edge_cap, st, true);
+  if (EMIT) wq_flush_block(qu, pairs, sc.edge_cap, &st->edges, &st->status, kStatusEdgeOverflow, xfer);
   __syncthreads();
   for (int t = threadIdx.x; t < c1 - c0; t += 256) {
     const int v = colcnt[t];

@@ -363,9 +363,10 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     ms.n = ni;
     ms.n_pad = npad;
     ms.d = d;
-    const Chunks c = split(npad / 32, npad / 256 * 4, 32LL * L.mfma_k * 2, 4);
-    ms.nchunks = c.nchunks;
-    ms.chunk = c.chunk;
+    // row chunks of 64 tiles (2048 rows; fewer for small n), 8 per column group
+    const int tiles = (int)(npad / 32);
+    ms.chunk = tiles < 64 ? tiles : 64;
+    ms.nchunks = (tiles + ms.chunk - 1) / ms.chunk;
     ms.pair_cap = L.edge_cap;
     ms.band_cap = L.band_cap;
     mark(4);

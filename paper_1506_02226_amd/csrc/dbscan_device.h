@@ -164,13 +164,20 @@ __device__ __forceinline__ void uf_union(int *parent, int a, int b) {
 }
 
 // ------------------------------------------------------- wave pair queue
-// A wave-private queue of (a, b) pairs in LDS (128 entries).  Ballots fill it
-// from whichever lanes found a pair; it is drained 64 pairs at a time so that
-// every lane of the wave works on one pair (union-find walks are latency
-// bound, so a full wave of independent walks hides the latency).
+// A wave-private queue of (a, b) pairs in LDS.  Ballots fill it from
+// whichever lanes found a pair.  Union queues (128 entries) are drained 64
+// pairs at a time so that every lane of the wave works on one pair (union-find
+// walks are latency bound, so a full wave of independent walks hides the
+// latency).  List queues are appended to a global list once `limit` pairs are
+// queued (the buffer holds limit + 64), with one atomic on the list cursor for
+// the whole batch: the cursor is shared by the whole grid.
+constexpr int kListQueue = 320;  // list-queue buffer (pairs)
+constexpr int kListDrain = 256;  // ... appended to the global list at this fill
+
 struct WaveQueue {
   int2 *buf;
   int count;  // wave-uniform
+  int limit;  // list queues: append once this many are queued
 };
 
 __device__ __forceinline__ void wq_push(WaveQueue &q, bool has, int a, int b) {
@@ -202,25 +209,50 @@ __device__ __forceinline__ void wq_drain_union(WaveQueue &q, int *parent, bool a
   }
 }
 
-// Append the queued pairs to a global list at *cursor; past `cap` entries the
-// pairs are dropped and `flag` is raised in the status word.
+// Append the queued pairs to a global list at *cursor (when at least q.limit
+// are queued, or any when `all`); past `cap` entries the pairs are dropped
+// and `flag` is raised in the status word.
 __device__ __forceinline__ void wq_drain_to(WaveQueue &q, int2 *list, long long cap,
                                             unsigned long long *cursor, unsigned *status,
                                             unsigned flag, bool all) {
-  while (q.count >= 64 || (all && q.count > 0)) {
-    const int take = q.count < 64 ? q.count : 64;
-    const int lane = lane_id();
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(cursor, (unsigned long long)take);
-    base = __shfl(base, 0);
-    if (lane < take) {
-      const unsigned long long idx = base + (unsigned long long)lane;
-      if (idx < (unsigned long long)cap) list[idx] = q.buf[lane];
-    }
-    if (lane == 0 && base + (unsigned long long)take > (unsigned long long)cap)
-      atomicOr(status, flag);
-    wq_pop(q, take);
+  if (q.count < q.limit && !(all && q.count > 0)) return;
+  const int lane = lane_id();
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(cursor, (unsigned long long)q.count);
+  base = __shfl(base, 0);
+  for (int k = lane; k < q.count; k += 64) {
+    const unsigned long long idx = base + (unsigned long long)k;
+    if (idx < (unsigned long long)cap) list[idx] = q.buf[k];
   }
+  if (lane == 0 && base + (unsigned long long)q.count > (unsigned long long)cap)
+    atomicOr(status, flag);
+  q.count = 0;
+}
+
+// End of a block: the leftovers of the 4 waves' queues go to the list with
+// one atomic for the block.  Every thread of the block calls it; `xfer` is 5
+// words of LDS.
+__device__ __forceinline__ void wq_flush_block(WaveQueue &q, int2 *list, long long cap,
+                                               unsigned long long *cursor, unsigned *status,
+                                               unsigned flag, unsigned long long *xfer) {
+  const int w = (int)(threadIdx.x >> 6), lane = lane_id();
+  if (lane == 0) xfer[w] = (unsigned long long)q.count;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned long long tot = xfer[0] + xfer[1] + xfer[2] + xfer[3];
+    const unsigned long long base = tot ? atomicAdd(cursor, tot) : 0ull;
+    if (tot && base + tot > (unsigned long long)cap) atomicOr(status, flag);
+    xfer[4] = base;
+  }
+  __syncthreads();
+  unsigned long long off = xfer[4];
+  for (int k = 0; k < w; ++k) off += xfer[k];
+  for (int k = lane; k < q.count; k += 64) {
+    const unsigned long long idx = off + (unsigned long long)k;
+    if (idx < (unsigned long long)cap) list[idx] = q.buf[k];
+  }
+  q.count = 0;
+  __syncthreads();  // xfer is reused by the next flush
 }
 
 // Neighbour pairs (i, j), j < i, for the merge.

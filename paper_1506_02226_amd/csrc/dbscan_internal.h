@@ -44,6 +44,15 @@ struct MfmaScalars {
   long long pair_cap, band_cap;
 };
 
+// Work items of the triangular matrix-core sweep: (column group g of 256
+// columns, row chunk c of 8k row tiles of 32) with c >= g / k (integer
+// division), listed column group by column group, so that blocks running at
+// the same time share columns and spread over rows.  Items before group g:
+__host__ __device__ inline long long mfma_items_before(int g, int nchunks, int k) {
+  const long long q = g / k, r = g - q * k;
+  return (long long)g * nchunks - (k * q * (q - 1) / 2 + q * r);
+}
+
 int rows_per_wave(int d);
 int coord_chunk(int d);
 

@@ -26,8 +26,9 @@ union ServeLds {
   MfmaLds<5> m;
   int2 q[4][128];
   struct {
-    int2 q[4][128];
+    int2 q[4][kListQueue];
     int colcnt[kServeTriChunk];
+    unsigned long long xfer[5];
   } t;
 };
 
@@ -106,10 +107,10 @@ __device__ __forceinline__ void run_task(const JobDesc &jd, int phase, int idx, 
       } else {
         const SweepScalars sc = plain_scalars(jd);
         switch (jd.d) {
-          case 1: count_tri_body<1, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
-          case 2: count_tri_body<2, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
-          case 3: count_tri_body<3, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
-          default: count_tri_body<4, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt); break;
+          case 1: count_tri_body<1, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt, lds.t.xfer); break;
+          case 2: count_tri_body<2, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt, lds.t.xfer); break;
+          case 3: count_tri_body<3, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt, lds.t.xfer); break;
+          default: count_tri_body<4, kServeRows, true>(jd.soa, jd.counts, jd.pairs, jd.st, sc, idx, lds.t.q, lds.t.colcnt, lds.t.xfer); break;
         }
       }
       break;

@@ -316,12 +316,14 @@ void dbscan_server::loop() {
       js.ntasks[dbk::kPhStage] = blocks256;
       js.ntasks[dbk::kPhThresh] = L.ks ? 1u : 0u;
       if (L.ks) {
-        // 256 stationary columns per task, rows split into tiles of 32
+        // 256 stationary columns per task, row chunks of <= 64 tiles of 32
+        // rows; only the lower triangle of (chunk, column group) is a task
         const int tiles = L.n_pad / 32;
-        const int per = tiles < 256 ? tiles : 256;  // <= 8192 rows per task
+        const int per = tiles < 64 ? tiles : 64;
         jd.chunk = per;
         jd.nchunks = (tiles + per - 1) / per;
-        js.ntasks[dbk::kPhCount] = blocks256 * (unsigned)jd.nchunks;
+        js.ntasks[dbk::kPhCount] =
+            (unsigned)dbk::mfma_items_before((int)blocks256, jd.nchunks, per / 8);
       } else {
         // triangular sweep: 128 rows x a column chunk of <= 4096 per task
         jd.chunk = L.n_pad < dbk::kServeTriChunk ? L.n_pad : dbk::kServeTriChunk;

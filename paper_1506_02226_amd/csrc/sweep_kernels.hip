@@ -4,8 +4,9 @@
 // d <= 4 or in LDS otherwise -- and the 64 lanes hold 64 columns, so one
 // compare yields one 64-bit ballot word of the primitive cluster of a row.
 //
-//  * k_count_small: step 1 + counts; also appends every neighbour pair
-//    (i, j), j < i, to a pair list (the input of the merge) while it fits.
+//  * k_count_tri: step 1 + counts, each unordered pair tested once; also
+//    appends every neighbour pair (i, j), j < i, to a pair list (the input of
+//    the merge) while it fits.
 //  * k_union_small / k_border_small: the merge and the border pass repeated
 //    on the fly; they run only when the pair list overflowed (or always, for
 //    the border pass of the bitmask form).
@@ -30,16 +31,6 @@ __device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevStat
 }
 
 // ------------------------------------------------- step 1 + counts, d <= 4
-template <int D, int R, bool EMIT>
-__global__ __launch_bounds__(256) void k_count_small(const float *__restrict__ soa,
-                                                     int *__restrict__ counts,
-                                                     int2 *__restrict__ pairs,
-                                                     DevState *__restrict__ st, SweepScalars sc) {
-  __shared__ int2 qbuf[4][128];
-  if (skip_sweep(sc, st)) return;
-  count_small_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf);
-}
-
 // Triangular form (each unordered pair tested once); LDS column tallies.
 constexpr int kTriMaxChunk = 4096;
 
@@ -48,10 +39,11 @@ __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa
                                                    int *__restrict__ counts,
                                                    int2 *__restrict__ pairs,
                                                    DevState *__restrict__ st, SweepScalars sc) {
-  __shared__ int2 qbuf[4][128];
+  __shared__ int2 qbuf[4][kListQueue];
   __shared__ int colcnt[kTriMaxChunk];
+  __shared__ unsigned long long xfer[5];
   if (skip_sweep(sc, st)) return;
-  count_tri_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt);
+  count_tri_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
 }
 
 // --------------------------------------- merge repeated on the fly, d <= 4
@@ -84,7 +76,7 @@ __global__ __launch_bounds__(256) void k_union_small(const float *__restrict__ s
   for (int r = 0; r < R; ++r)
 #pragma unroll
     for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
-  WaveQueue qu{qbuf[w], 0};
+  WaveQueue qu{qbuf[w], 0, 64};
   for (int cb = 0; cb < c1; cb += 64) {
     const uint64_t cw = (uint64_t)corebits[cb >> 5] | ((uint64_t)corebits[(cb >> 5) + 1] << 32);
     if (cw == 0ull) continue;
