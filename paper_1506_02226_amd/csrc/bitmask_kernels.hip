@@ -8,8 +8,9 @@
 namespace dbk {
 
 // ----------------------------------------------------- bitmask pass (d <= 4)
-// One wave takes 16 rows at a time (the "goal points" of Section IV-A.3, in
-// scalar registers) and the 64 lanes hold 64 columns.  Per row, one compare
+// One wave takes 16 rows at a time (the "goal points" of Section IV-A.3,
+// wave-uniform values held in vector registers so that the subtractions issue
+// at the full rate) and the 64 lanes hold 64 columns.  Per row, one compare
 // gives the 64-bit ballot of the row's neighbours among the columns (its
 // popcount is the row's count, on the scalar unit), and the same compare's
 // result is shifted into a per-lane 16-bit word with an add-with-carry
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(soa[(size_t)k * sc.n_pad + row0 + r]);
     // two rows' counts per scalar register (a chunk has at most 4096 columns)
     uint32_t cnt2[R / 2];
 #pragma unroll
@@ -89,7 +90,8 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
           const uint64_t lo_m = __ballot(s <= sc.lo);
           uint64_t in = m;
           if (lo_m != m) {
-            in = recheck_band<D>(m & ~lo_m, lo_m, xr[r], xc, sc.eps2, st);
+            in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
+                                  sc.eps2, st);
             word = (word & ~1u) | (uint32_t)((in >> lane) & 1ull);
           }
           cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);

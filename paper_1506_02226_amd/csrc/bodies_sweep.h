@@ -53,7 +53,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int k = 0; k < D; ++k) xr[r][k] = soa[(size_t)k * sc.n_pad + row0 + r];
+      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(soa[(size_t)k * sc.n_pad + row0 + r]);
     int cnt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) cnt[r] = 0;
@@ -83,7 +83,8 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
           const uint64_t lo_m = __ballot(s <= sc.lo);
           uint64_t in = m;
           if (lo_m != m) {
-            in = recheck_band<D>(m & ~lo_m, lo_m, xr[r], xc, sc.eps2, st);
+            in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
+                                  sc.eps2, st);
             tally -= (uint32_t)(((m ^ in) >> lane) & 1ull);  // in is a subset of m
           }
           cnt[r] += __popcll(in);
