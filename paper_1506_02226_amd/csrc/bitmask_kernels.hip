@@ -1,6 +1,6 @@
 // Bitmask form of steps 1 and 3 (d <= 4): the neighbour relation kept as one
 // bit per ordered pair -- the paper's `cluster` matrix of Section IV-B, at one
-// bit instead of one byte per entry, in 16-bit words -- and the merge of
+// bit instead of one byte per entry, in 32-bit words -- and the merge of
 // Section IV-C read from it.
 #include "dbscan_device.h"
 #include "dbscan_internal.h"
@@ -8,38 +8,38 @@
 namespace dbk {
 
 // ----------------------------------------------------- bitmask pass (d <= 4)
-// One wave takes 16 rows at a time (the "goal points" of Section IV-A.3,
+// One wave takes 32 rows at a time (the "goal points" of Section IV-A.3,
 // wave-uniform values held in vector registers so that the subtractions issue
 // at the full rate) and the 64 lanes hold 64 columns.  Per row, one compare
 // gives the 64-bit ballot of the row's neighbours among the columns (its
 // popcount is the row's count, on the scalar unit), and the same compare's
-// result is shifted into a per-lane 16-bit word with an add-with-carry
-// (w = 2w + bit).  After the 16 rows, lane j holds the pairs (rows
-// row0..row0+15, column j); by symmetry that is row j's word for the columns
-// row0..row0+15, stored at adj[row0/16][j] -- a coalesced 128-byte store per
-// wave.  Bit b of adj[q][i] is the pair (i, 16q+b).  Padded rows and columns
+// result is shifted into a per-lane 32-bit word with an add-with-carry
+// (w = 2w + bit).  After the 32 rows, lane j holds the pairs (rows
+// row0..row0+31, column j); by symmetry that is row j's word for the columns
+// row0..row0+31, stored at adj[row0/32][j] -- a coalesced 256-byte store per
+// wave.  Bit b of adj[q][i] is the pair (i, 32q+b).  Padded rows and columns
 // (index >= n) are NaN, so their bits are zero.
 //
 // The relation is symmetric, so each unordered pair is tested once: a 16-row
 // block only visits the 64-column blocks from the one holding its own rows
-// onwards.  That stores adj[q][i] for every i >= 16q (all the lower triangle
+// onwards.  That stores adj[q][i] for every i >= 32q (all the lower triangle
 // the merge reads), and the counts come from both sides of each test: the
 // row side as ballot popcounts in scalar registers, the column side as the
 // popcount of the lane's word, summed per block in LDS and added to counts[]
 // once per block.  In the diagonal 64x64 block every row visits all 64
 // columns itself, so column sums are taken only off that block.
 //
-// A block owns sc.rgroup rows (4 waves, 16-row blocks dealt round-robin) and
+// A block owns sc.rgroup rows (4 waves, 32-row blocks dealt round-robin) and
 // the sc.chunk columns of one chunk; the grid is row groups x chunks, and a
 // block whose columns all lie before its rows has nothing to do.
 constexpr int kBitmaskMaxChunk = 4096;
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
-                                                 uint16_t *__restrict__ adj,
+                                                 uint32_t *__restrict__ adj,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
-  constexpr int R = 16;
+  constexpr int R = 32;
   __shared__ int colcnt[kBitmaskMaxChunk];
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
     uint32_t cnt2[R / 2];
 #pragma unroll
     for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
-    uint16_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
+    uint32_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
     float xn[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
           cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
         }
       }
-      out[cb + lane] = (uint16_t)word;
+      out[cb + lane] = word;
       if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
     }
     int mine = 0;
@@ -116,8 +116,9 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 
 // --------------------------------------------------- merge from the bitmask
 // Step 3 and the border points in one read of the lower triangle.  One wave
-// owns 64 rows i (lanes) and walks the 16-column words q of a chunk up to the
-// diagonal, so it sees every neighbour pair (i, j), j < i, once:
+// owns 64 rows i (lanes) and walks the 32-column words q of a chunk up to the
+// diagonal, so it sees every neighbour pair (i, j), j < i, once, and takes
+// the set bits of its word one per lane per round:
 //  * core i, core j: queued, and the queue is drained into the union-find 64
 //    pairs at a time;
 //  * core i, non-core j: i is a core neighbour of j (atomicMin on jstar[j]);
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 // A non-core point's core neighbours above it are found by those rows, so
 // after the pass jstar[v] is the lowest-index core neighbour of every
 // non-core v.
-__global__ __launch_bounds__(256) void k_merge_bitmask(const uint16_t *__restrict__ adj,
+__global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restrict__ adj,
                                                        const uint32_t *__restrict__ corebits,
                                                        int *__restrict__ parent,
                                                        int *__restrict__ jstar,
@@ -141,9 +142,9 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint16_t *__restric
   const bool valid = i < p.n;
   const bool is_core = valid && ((corebits[i >> 5] >> (i & 31)) & 1u);
   bool seek = valid && !is_core;
-  const int qi = i >> 4;
+  const int qi = i >> 5;
   const int q0 = chunk * p.chunk;
-  const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 16 + 1);  // lower triangle
+  const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 32 + 1);  // lower triangle
   if (q0 >= q1) return;
   WaveQueue qu{qbuf[w], 0, 64};
   // kU words per lane are loaded before any is used, so that kU loads per
@@ -154,31 +155,33 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint16_t *__restric
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int q = qb + u;
-      wv[u] = (q < q1) ? (uint32_t)adj[(size_t)q * p.n_pad + i] : 0u;
+      wv[u] = (q < q1) ? adj[(size_t)q * p.n_pad + i] : 0u;
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int q = qb + u;
-      const uint32_t cw = (q < q1) ? ((corebits[q >> 1] >> ((q & 1) * 16)) & 0xffffu) : 0u;
       uint32_t word = wv[u];
       if (!valid || q > qi || q >= q1) word = 0u;
-      else if (q == qi) word &= (1u << (i & 15)) - 1u;
-      const uint32_t hit = word & cw;
-      if (seek && hit != 0u) {
-        atomicMin(jstar + i, q * 16 + __builtin_ctz(hit));
-        seek = false;
+      else if (q == qi) word &= (1u << (i & 31)) - 1u;
+      if (__ballot(word != 0u) == 0ull) continue;
+      const uint32_t cw = corebits[q];  // core flags of the columns 32q..32q+31
+      if (!is_core) {
+        // the first core neighbour of a non-core row, in ascending order
+        const uint32_t hit = word & cw;
+        if (seek && hit != 0u) {
+          atomicMin(jstar + i, q * 32 + __builtin_ctz(hit));
+          seek = false;
+        }
+        word = 0u;
       }
-      uint32_t bw = is_core ? (word & ~cw) : 0u;
-      while (bw != 0u) {
-        atomicMin(jstar + q * 16 + __builtin_ctz(bw), i);
-        bw &= bw - 1u;
-      }
-      uint32_t uw = is_core ? hit : 0u;
-      while (__ballot(uw != 0u) != 0ull) {
-        const bool has = uw != 0u;
-        const int j = q * 16 + (has ? __builtin_ctz(uw) : 0);
-        uw &= uw - 1u;
-        wq_push(qu, has, i, j);
+      while (__ballot(word != 0u) != 0ull) {
+        const bool has = word != 0u;
+        const int b = has ? __builtin_ctz(word) : 0;
+        word &= word - 1u;
+        const int j = q * 32 + b;
+        const bool cj = (cw >> b) & 1u;
+        if (has && is_core && !cj) atomicMin(jstar + j, i);
+        wq_push(qu, has && is_core && cj, i, j);
         wq_drain_union(qu, parent, false);
       }
     }
@@ -193,10 +196,10 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
   const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
   const dim3 grid(groups * sc.nchunks), block(256);
   switch (sc.d) {
-    case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint16_t *)b.adjT, b.counts, b.st, sc); break;
-    case 2: hipLaunchKernelGGL(k_bitmask<2>, grid, block, 0, s, b.soa, (uint16_t *)b.adjT, b.counts, b.st, sc); break;
-    case 3: hipLaunchKernelGGL(k_bitmask<3>, grid, block, 0, s, b.soa, (uint16_t *)b.adjT, b.counts, b.st, sc); break;
-    case 4: hipLaunchKernelGGL(k_bitmask<4>, grid, block, 0, s, b.soa, (uint16_t *)b.adjT, b.counts, b.st, sc); break;
+    case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
+    case 2: hipLaunchKernelGGL(k_bitmask<2>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
+    case 3: hipLaunchKernelGGL(k_bitmask<3>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
+    case 4: hipLaunchKernelGGL(k_bitmask<4>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -205,7 +208,7 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
   hipLaunchKernelGGL(k_merge_bitmask, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                     (const uint16_t *)b.adjT, b.corebits, b.parent, b.jstar, sc);
+                     (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, sc);
   return hipGetLastError();
 }
 

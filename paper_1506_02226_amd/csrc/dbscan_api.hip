@@ -38,7 +38,7 @@ struct Layout {
   int mfma_k = 0;        // contraction length of the matrix-core filter
 };
 
-uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 16 * (uint64_t)n_pad * 2; }
+uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
 
 int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->n_pad = round_up(n, kPadRows);
@@ -408,7 +408,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     b3.chunk = c.chunk * 64;
   }
   if (bitmask) {
-    const Chunks c = split(npad / 16, npad / 64, 1, 8);
+    const Chunks c = split(npad / 32, npad / 64, 1, 8);
     dbk::SweepScalars u3 = sc;
     u3.nchunks = c.nchunks;
     u3.chunk = c.chunk;
