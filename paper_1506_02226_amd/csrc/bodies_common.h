@@ -8,12 +8,11 @@
 
 namespace dbk {
 
-// soa[k][i] = points[i][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n.
-// Also clears counts, parent = identity, jstar = none; flags non-finite input.
-__device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n, int d, int n_pad,
-                                           int d_pad, float *__restrict__ soa,
-                                           int *__restrict__ counts, int *__restrict__ parent,
-                                           int *__restrict__ jstar, DevState *st, int bid) {
+// soa[k][i] = points[i][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n;
+// flags non-finite input.
+__device__ __forceinline__ void stage_soa_body(const float *__restrict__ pts, int n, int d,
+                                               int n_pad, int d_pad, float *__restrict__ soa,
+                                               DevState *st, int bid) {
   const int i = bid * 256 + (int)threadIdx.x;
   if (i >= n_pad) return;
   bool bad = false;
@@ -28,12 +27,22 @@ __device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n,
     }
     soa[(size_t)k * n_pad + i] = v;
   }
+  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNonFinite);
+}
+
+// Clears counts, parent = identity, jstar = none; with `soa`, also stages the
+// coordinates (stage_soa_body).
+__device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n, int d, int n_pad,
+                                           int d_pad, float *__restrict__ soa,
+                                           int *__restrict__ counts, int *__restrict__ parent,
+                                           int *__restrict__ jstar, DevState *st, int bid) {
+  if (soa) stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, bid);
+  const int i = bid * 256 + (int)threadIdx.x;
   if (i < n) {
     counts[i] = 0;
     parent[i] = i;
     jstar[i] = kNoNeighbour;
   }
-  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNonFinite);
 }
 
 // ------------------------------------------------------------- core flags

@@ -41,63 +41,91 @@ template <> struct LowPrec<_Float16> {
 };
 
 // ---------------------------------------------------------------- prepare
-// One thread per (padded) point: rounded coordinates, FP32 norm of the
-// rounded point split hi + lo, both augmented rows, and the float64 norm of
-// the original point for the bounds (max via an atomic on its bit pattern).
+// A block prepares 256 (padded) points, each wave 64 of them one after the
+// other with the lanes over the coordinates (coalesced loads and stores):
+// rounded coordinates, the FP32 norm of the rounded point (a wave sum, split
+// hi + lo), both augmented rows, and the float64 norm of the original point
+// for the bounds (max via an atomic on its bit pattern).  K <= 128.
 template <typename T>
 __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, int n, int d,
                                                int n_pad, int K, T *__restrict__ a_aug,
                                                T *__restrict__ b_aug, DevState *st, int bid) {
-  const int i = bid * 256 + (int)threadIdx.x;
-  if (i >= n_pad) return;
-  T *a = a_aug + (size_t)i * K;
-  T *b = b_aug + (size_t)i * K;
-  bool bad = false;
-  if (i < n) {
-    float nrm = 0.0f;
-    double nrm64 = 0.0;
-    for (int k = 0; k < d; ++k) {
-      const float x = pts[(size_t)i * d + k];
-      bad |= !__builtin_isfinite(x) || __builtin_fabsf(x) > LowPrec<T>::maxval;
-      const T xr = (T)x;
-      const float xf = (float)xr;
-      nrm = __builtin_fmaf(xf, xf, nrm);
-      nrm64 += (double)x * (double)x;
-      a[k] = xr;
-      b[k] = (T)(-2.0f * xf);
+  const int lane = lane_id();
+  const int w = (int)(threadIdx.x >> 6);
+  bool bad = false, nonfinite = false;
+  double mx = 0.0;
+  for (int t = 0; t < 64; ++t) {
+    const int i = bid * 256 + w * 64 + t;  // wave-uniform
+    if (i >= n_pad) break;
+    T *a = a_aug + (size_t)i * K;
+    T *b = b_aug + (size_t)i * K;
+    if (i < n) {
+      float part = 0.0f;
+      double part64 = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        if (k < d) {
+          const float x = pts[(size_t)i * d + k];
+          nonfinite |= !__builtin_isfinite(x);
+          bad |= nonfinite || __builtin_fabsf(x) > LowPrec<T>::maxval;
+          const T xr = (T)x;
+          const float xf = (float)xr;
+          part = __builtin_fmaf(xf, xf, part);
+          part64 += (double)x * (double)x;
+          a[k] = xr;
+          b[k] = (T)(-2.0f * xf);
+        } else if (k >= d + 4 && k < K) {
+          a[k] = (T)0.0f;
+          b[k] = (T)0.0f;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        part += __shfl_xor(part, off);
+        part64 += __shfl_xor(part64, off);
+      }
+      const float nrm = part;  // same value in every lane
+      bad |= !(nrm <= LowPrec<T>::maxval);
+      const T hi = (T)nrm;
+      const T lo = (T)(nrm - (float)hi);
+      if (lane == 0) {
+        a[d] = hi;
+        a[d + 1] = lo;
+        a[d + 2] = (T)1.0f;
+        a[d + 3] = (T)1.0f;
+        b[d] = (T)1.0f;
+        b[d + 1] = (T)1.0f;
+        b[d + 2] = hi;
+        b[d + 3] = lo;
+      }
+      mx = part64 > mx ? part64 : mx;
+    } else {
+      // padding: a norm so large that no padded pair can reach the band
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = lane + 64 * h;
+        if (k < K && (k < d || k >= d + 4)) {
+          a[k] = (T)0.0f;
+          b[k] = (T)0.0f;
+        }
+      }
+      if (lane == 0) {
+        a[d] = (T)LowPrec<T>::big;
+        a[d + 1] = (T)0.0f;
+        a[d + 2] = (T)1.0f;
+        a[d + 3] = (T)1.0f;
+        b[d] = (T)1.0f;
+        b[d + 1] = (T)1.0f;
+        b[d + 2] = (T)LowPrec<T>::big;
+        b[d + 3] = (T)0.0f;
+      }
     }
-    bad |= !(nrm <= LowPrec<T>::maxval);
-    const T hi = (T)nrm;
-    const T lo = (T)(nrm - (float)hi);
-    a[d] = hi;
-    a[d + 1] = lo;
-    a[d + 2] = (T)1.0f;
-    a[d + 3] = (T)1.0f;
-    b[d] = (T)1.0f;
-    b[d + 1] = (T)1.0f;
-    b[d + 2] = hi;
-    b[d + 3] = lo;
-    const double m = __builtin_sqrt(nrm64);
-    atomicMax(&st->max_norm, (unsigned long long)__double_as_longlong(m));
-  } else {
-    for (int k = 0; k < d; ++k) {
-      a[k] = (T)0.0f;
-      b[k] = (T)0.0f;
-    }
-    a[d] = (T)LowPrec<T>::big;
-    a[d + 1] = (T)0.0f;
-    a[d + 2] = (T)1.0f;
-    a[d + 3] = (T)1.0f;
-    b[d] = (T)1.0f;
-    b[d + 1] = (T)1.0f;
-    b[d + 2] = (T)LowPrec<T>::big;
-    b[d + 3] = (T)0.0f;
   }
-  for (int k = d + 4; k < K; ++k) {
-    a[k] = (T)0.0f;
-    b[k] = (T)0.0f;
-  }
-  if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusRange);
+  if (lane == 0 && mx > 0.0)
+    atomicMax(&st->max_norm, (unsigned long long)__double_as_longlong(__builtin_sqrt(mx)));
+  if (__ballot(bad) != 0ull && lane == 0) atomicOr(&st->status, kStatusRange);
+  if (__ballot(nonfinite) != 0ull && lane == 0) atomicOr(&st->status, kStatusNonFinite);
 }
 
 // ------------------------------------------------------------- thresholds

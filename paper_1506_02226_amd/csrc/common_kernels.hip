@@ -83,10 +83,16 @@ __global__ void k_labels(int n, const uint8_t *__restrict__ core, const int *__r
 // When the matrix-core filter gave up (inputs out of its range, or too many
 // undecided pairs), clear the counts for the float32 sweep that redoes step 1
 // and mark the pair list as incomplete so that step 3 repeats the tests.
-__global__ void k_filter_fallback(int *__restrict__ counts, int n, DevState *st) {
+// When the matrix-core filter gave up: clear the counts, stage the float32
+// coordinates for the sweeps that redo step 1 (the filtered path does not
+// need them), and mark the pair list incomplete so step 3 repeats the tests.
+__global__ void k_filter_fallback(const float *__restrict__ pts, int n, int d, int n_pad,
+                                  int d_pad, float *__restrict__ soa, int *__restrict__ counts,
+                                  DevState *st) {
   const unsigned status =
       __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!(status & (kStatusRange | kStatusBandOverflow))) return;
+  stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, blockIdx.x);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) counts[i] = 0;
   if (i == 0) atomicOr(&st->status, kStatusEdgeOverflow);
@@ -125,8 +131,10 @@ hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t run_filter_fallback(int *counts, int n, DevState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_filter_fallback, dim3((n + 255) / 256), dim3(256), 0, s, counts, n, st);
+hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_pad, float *soa,
+                               int *counts, DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_fallback, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, n, d,
+                     n_pad, d_pad, soa, counts, st);
   return hipGetLastError();
 }
 

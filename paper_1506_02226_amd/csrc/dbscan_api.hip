@@ -325,7 +325,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   };
 
   step(dbk::run_reset(st, s));
-  step(dbk::run_stage(points, ni, d, npad, L.d_pad, soa, counts, parent, jstar, st, s));
+  // the matrix-core path stages the float32 coordinates only if it falls back
+  step(dbk::run_stage(points, ni, d, npad, L.d_pad, mfma ? nullptr : soa, counts, parent, jstar,
+                      st, s));
   const double band_rel = (opts && opts->band_rel > 0.0) ? opts->band_rel : kDefaultBandRel;
   if (mfma) {
     step(dbk::run_mfma_prep(points, ni, d, npad, L.precision, a_aug, b_aug, st, s));
@@ -374,7 +376,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     mark(5);
     step(dbk::run_recheck_band(points, d, bufs, eps2, L.band_cap, L.edge_cap, s));
     // the float32 sweep redoes step 1 only if the filter gave up
-    step(dbk::run_filter_fallback(counts, ni, st, s));
+    step(dbk::run_filter_fallback(points, ni, d, npad, L.d_pad, soa, counts, st, s));
     dbk::SweepScalars f1 = sweep_tiles(sc, n, npad, d, L.d_pad);
     f1.flags = dbk::kOnlyOnFilterFail;
     step(dbk::run_count(bufs, f1, false, s));

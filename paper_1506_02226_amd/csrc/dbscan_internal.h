@@ -68,7 +68,8 @@ hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *co
 hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
-hipError_t run_filter_fallback(int *counts, int n, DevState *st, hipStream_t s);
+hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_pad, float *soa,
+                               int *counts, DevState *st, hipStream_t s);
 
 int mfma_k(int d);
 hipError_t run_mfma_prep(const float *pts, int n, int d, int n_pad, int prec, void *a_aug,

@@ -186,16 +186,16 @@ __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ 
 // lanes, coordinates processed DC at a time.  Same three modes as above.
 enum { MODE_COUNT = 0, MODE_UNION = 1, MODE_BORDER = 2 };
 
+// One block's work (`bid` = its index in the full grid).
 template <int DC, int R, int MODE>
-__global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
-                                                  int *__restrict__ counts,
-                                                  const uint32_t *__restrict__ corebits,
-                                                  int *__restrict__ parent,
-                                                  const int *__restrict__ list,
-                                                  int *__restrict__ jstar,
-                                                  DevState *__restrict__ st, SweepScalars sc) {
-  extern __shared__ float lds_rows[];
-  if (skip_sweep(sc, st)) return;
+__device__ __forceinline__ void rows_lds_block(const float *__restrict__ soa,
+                                               int *__restrict__ counts,
+                                               const uint32_t *__restrict__ corebits,
+                                               int *__restrict__ parent,
+                                               const int *__restrict__ list,
+                                               int *__restrict__ jstar,
+                                               DevState *__restrict__ st, const SweepScalars &sc,
+                                               float *lds_rows, int bid) {
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
   const int n = sc.n;
@@ -203,8 +203,8 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
   uint32_t active = 0;
   int cb_begin = 0, cb_end = sc.n_pad;
   if (MODE == MODE_COUNT) {
-    const int chunk = blockIdx.x % sc.nchunks;
-    const int rb = (blockIdx.x / sc.nchunks) * 4 + w;
+    const int chunk = bid % sc.nchunks;
+    const int rb = (bid / sc.nchunks) * 4 + w;
     cb_begin = chunk * sc.chunk;
     cb_end = min(cb_begin + sc.chunk, sc.n_pad);
 #pragma unroll
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
     }
   } else if (MODE == MODE_UNION) {
     const int total = (n + R - 1) / R;
-    const int rb = total - 1 - (int)(blockIdx.x * 4 + w);
+    const int rb = total - 1 - (int)(bid * 4 + w);
     int last = -1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
   } else {
     const int listed = wave_uniform((int)__hip_atomic_load(&st->noncore, __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_AGENT));
-    const int e0 = (blockIdx.x * 4 + w) * R;
+    const int e0 = (bid * 4 + w) * R;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       rows[r] = 0;
@@ -328,6 +328,26 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
   }
 }
 
+// The sweep kernel.  A fallback launch (sc.flags set) usually has nothing to
+// do, so it runs on a small grid that strides over the `nblocks` blocks of
+// the full launch instead of launching them all.
+template <int DC, int R, int MODE>
+__global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
+                                                  int *__restrict__ counts,
+                                                  const uint32_t *__restrict__ corebits,
+                                                  int *__restrict__ parent,
+                                                  const int *__restrict__ list,
+                                                  int *__restrict__ jstar,
+                                                  DevState *__restrict__ st, SweepScalars sc,
+                                                  int nblocks) {
+  extern __shared__ float lds_rows[];
+  if (skip_sweep(sc, st)) return;
+  for (int bid = blockIdx.x; bid < nblocks; bid += gridDim.x) {
+    rows_lds_block<DC, R, MODE>(soa, counts, corebits, parent, list, jstar, st, sc, lds_rows, bid);
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ host launchers
 constexpr int kRowsSmall = 8;  // rows per wave, d <= 4 (scalar registers)
 constexpr int kRowsLds = 8;    // rows per wave, d > 4 (LDS)
@@ -345,11 +365,14 @@ int coord_chunk(int d) {
 template <int MODE>
 static hipError_t launch_lds(const Buffers &b, const SweepScalars &sc, int blocks, hipStream_t s) {
   const size_t lds = (size_t)4 * kRowsLds * sc.d_pad * sizeof(float);
+  const int grid = (sc.flags && blocks > 2048) ? 2048 : blocks;
+  if (blocks <= 0) return hipSuccess;
   switch (coord_chunk(sc.d)) {
 #define DBK_LDS_CASE(DC)                                                                      \
   case DC:                                                                                    \
-    hipLaunchKernelGGL((k_rows_lds<DC, kRowsLds, MODE>), dim3(blocks), dim3(256), lds, s,    \
-                       b.soa, b.counts, b.corebits, b.parent, b.list, b.jstar, b.st, sc);     \
+    hipLaunchKernelGGL((k_rows_lds<DC, kRowsLds, MODE>), dim3(grid), dim3(256), lds, s,      \
+                       b.soa, b.counts, b.corebits, b.parent, b.list, b.jstar, b.st, sc,      \
+                       blocks);                                                               \
     break;
     DBK_LDS_CASE(8)
     DBK_LDS_CASE(16)
