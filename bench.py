@@ -307,7 +307,7 @@ def main(argv=None) -> int:
     else:
         achieved = tests * valu_ops_per_pair(d) / (k_ms * 1e-3) / 1e12
         kernel = "k_bitmask" if st["adjacency_used"] == "bitmask" else (
-            "k_count_tri" if d <= 4 else "k_rows_lds")
+            "k_count_tri" if d <= 4 else "k_count_tri_lds")
         roof = {"bound": "alu", "kernel": kernel, "achieved": round(achieved, 3),
                 "peak": round(VALU_LANE_OPS_PEAK / 1e12, 3), "unit": "Tlane-op/s",
                 "frac": round(achieved * 1e12 / VALU_LANE_OPS_PEAK, 4), "traffic": None,

@@ -87,7 +87,7 @@ typedef struct dbscan_opts {
                                  dbscan_workspace_size() bytes, 256-byte aligned.
                                  NULL: the library allocates it stream-ordered. */
   uint64_t workspace_bytes;
-  uint64_t pair_capacity;     /* on-the-fly form, d <= 4: room for this many
+  uint64_t pair_capacity;     /* on-the-fly form (any d): room for this many
                                  neighbour pairs (i, j), j < i, recorded by step 1
                                  for the merge (8 bytes each; 0 = 128 per point).
                                  If they do not fit, step 3 repeats the epsilon
@@ -127,10 +127,10 @@ typedef struct dbscan_stats {
                              redone in float32, else 0 */
   float ms_sweep1;        /* the step-1 sweep kernel alone, device time */
   int64_t sweep1_tests;   /* pair tests that kernel makes: about n^2/2 for the
-                             triangular float32 sweeps (d <= 4; each unordered
-                             pair once, both orders inside 64x64 diagonal
-                             blocks), n_pad^2 for the matrix-core tiles, about
-                             n*n_pad for d > 4 in float32 */
+                             triangular float32 sweeps (each unordered pair
+                             once, both orders inside 64x64 diagonal blocks)
+                             and for the matrix-core tiles (256x256 diagonal
+                             zones) */
 } dbscan_stats;
 
 /*

@@ -84,7 +84,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->off_corebits = take((uint64_t)L->n_pad / 8);
   L->off_list = take((uint64_t)L->n_pad * 4);
   L->off_adj = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(bitmask_bytes(L->n_pad)) : off;
-  if (L->adjacency == DBSCAN_ADJ_ONTHEFLY && (d <= 4 || mfma)) {
+  if (L->adjacency == DBSCAN_ADJ_ONTHEFLY) {
     const uint64_t req = (o && o->pair_capacity) ? o->pair_capacity : (uint64_t)kPairsPerPoint * n;
     L->edge_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
   }
@@ -188,17 +188,13 @@ Tri tri_split(int64_t n_pad, int max_chunk) {
 dbk::SweepScalars sweep_tiles(const dbk::SweepScalars &sc, int64_t n, int64_t npad, int d,
                               int d_pad) {
   dbk::SweepScalars t = sc;
-  if (d <= 4) {
-    const Tri tr = tri_split(npad, 4096);
-    t.nchunks = tr.nchunks;
-    t.chunk = tr.chunk;
-    t.rgroup = tr.rgroup;
-  } else {
-    const int R = dbk::rows_per_wave(d);
-    const Chunks c = split(npad / 64, (n + R - 1) / R, 64LL * d_pad * 4, 2);
-    t.nchunks = c.nchunks;
-    t.chunk = c.chunk * 64;
-  }
+  const Tri tr = tri_split(npad, 4096);
+  t.nchunks = tr.nchunks;
+  t.chunk = tr.chunk;
+  t.rgroup = tr.rgroup;
+  (void)n;
+  (void)d;
+  (void)d_pad;
   return t;
 }
 
@@ -209,10 +205,9 @@ int64_t sweep_tests(int64_t n, int64_t n_pad, int d, bool bitmask, bool mfma) {
     const int64_t G = n_pad / 256;
     return 65536 * G * (G + 1) / 2;
   }
-  if (d > 4) return n * n_pad;
-  // 16-row (bitmask) or 8-row blocks from row 0 while below n_pad / n, each
+  // 32-row (bitmask) or 8-row blocks from row 0 while below n_pad / n, each
   // testing the columns from its own 64-column diagonal block to n_pad
-  const int64_t R = bitmask ? 16 : dbk::rows_per_wave(d);
+  const int64_t R = bitmask ? 32 : dbk::rows_per_wave(d);
   const int64_t rows_end = bitmask ? n_pad : n;
   int64_t t = 0;
   for (int64_t row0 = 0; row0 < rows_end; row0 += R) t += R * (n_pad - (row0 & ~63LL));

@@ -181,6 +181,121 @@ __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ 
   }
 }
 
+// ------------------------------------- step 1 + counts, d > 4, triangular
+// The tiling of count_tri_body (blocks of sc.rgroup rows x sc.chunk columns,
+// R-row blocks from their own diagonal 64-column block on, row counts from
+// ballots, column counts from per-lane tallies summed in LDS, pair list
+// through wave queues), with the R rows of a wave staged in LDS (d_pad
+// floats each, read as broadcasts) and the coordinates taken DC at a time.
+template <int DC, int R, bool EMIT>
+__global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__ soa,
+                                                       int *__restrict__ counts,
+                                                       int2 *__restrict__ pairs,
+                                                       DevState *__restrict__ st,
+                                                       SweepScalars sc) {
+  extern __shared__ float lds_rows[];  // [4][R][d_pad]
+  __shared__ int2 qbuf[4][kListQueue];
+  __shared__ int colcnt[kTriMaxChunk];
+  __shared__ unsigned long long xfer[5];
+  if (skip_sweep(sc, st)) return;
+  const int lane = lane_id();
+  const int w = wave_uniform(threadIdx.x >> 6);
+  const int chunk = blockIdx.x % sc.nchunks;
+  const int g0 = (blockIdx.x / sc.nchunks) * sc.rgroup;
+  const int c0 = chunk * sc.chunk;
+  const int c1 = min(c0 + sc.chunk, sc.n_pad);
+  if (g0 >= sc.n || c1 <= g0) return;  // block-uniform
+  for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
+  __syncthreads();
+  const int g1 = min(g0 + sc.rgroup, sc.n);
+  const int dp = sc.d_pad;
+  float *my_rows = lds_rows + (size_t)w * R * dp;
+  WaveQueue qu{qbuf[w], 0, kListDrain};
+  for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
+    const int diag = row0 & ~63;
+    const int cs = max(c0, diag);
+    if (cs >= c1) continue;  // wave-uniform
+    // this wave's rows (only this wave reads them; LDS is in order per wave)
+    for (int e = lane; e < R * dp; e += 64) {
+      const int r = e / dp, k = e - r * dp;
+      my_rows[e] = soa[(size_t)k * sc.n_pad + row0 + r];  // padded rows are NaN
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    int cnt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) cnt[r] = 0;
+    for (int cb = cs; cb < c1; cb += 64) {
+      const int j = cb + lane;
+      float s[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[r] = 0.0f;
+      for (int kc = 0; kc < dp; kc += DC) {
+        float xc[DC];
+#pragma unroll
+        for (int k = 0; k < DC; ++k) xc[k] = soa[(size_t)(kc + k) * sc.n_pad + j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float *xrow = my_rows + r * dp + kc;
+          float a = s[r];
+#pragma unroll
+          for (int k = 0; k < DC; ++k) {
+            const float t = xrow[k] - xc[k];
+            a = __builtin_fmaf(t, t, a);
+          }
+          s[r] = a;
+        }
+      }
+      const bool off = cb != diag;
+      uint32_t tally = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        uint64_t m, carry;
+        // m = ballot(s <= hi); tally += this lane's bit of m
+        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
+            "v_addc_co_u32_e64 %0, %2, %0, 0, %1"
+            : "+v"(tally), "=&s"(m), "=&s"(carry)
+            : "s"(sc.hi), "v"(s[r]));
+        if (m != 0ull) {
+          const uint64_t lo_m = __ballot(s[r] <= sc.lo);
+          uint64_t in = m;
+          if (lo_m != m) {
+            const uint64_t band = m & ~lo_m;
+            bool ex = false;
+            if ((band >> lane) & 1ull)
+              ex = exact_within_mem(my_rows + r * dp, 1, soa + j, sc.n_pad, sc.d, sc.eps2);
+            in = lo_m | __ballot(ex);
+            if (lane == 0) atomicAdd(&st->band_pairs, (unsigned long long)__popcll(band));
+            tally -= (uint32_t)(((m ^ in) >> lane) & 1ull);  // in is a subset of m
+          }
+          cnt[r] += __popcll(in);
+          if (EMIT) {
+            if (off) {
+              wq_push(qu, (in >> lane) & 1ull, j, row0 + r);
+            } else {
+              const uint64_t e = in & below_mask(row0 + r, cb);
+              if (e != 0ull) wq_push(qu, (e >> lane) & 1ull, row0 + r, j);
+            }
+            wq_drain_list(qu, pairs, sc.edge_cap, st, false);
+          }
+        }
+      }
+      if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
+    }
+    int mine = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (lane == r) mine = cnt[r];
+    const int row = row0 + lane;
+    if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
+  }
+  if (EMIT) wq_flush_block(qu, pairs, sc.edge_cap, &st->edges, &st->status, kStatusEdgeOverflow, xfer);
+  __syncthreads();
+  for (int t = threadIdx.x; t < c1 - c0; t += 256) {
+    const int v = colcnt[t];
+    if (v != 0 && c0 + t < sc.n) atomicAdd(counts + c0 + t, v);
+  }
+}
+
 // ---------------------------------------------- row-uniform sweeps, any d
 // Rows staged in LDS ([4 waves][R][d_pad], read as broadcasts), columns in
 // lanes, coordinates processed DC at a time.  Same three modes as above.
@@ -385,14 +500,32 @@ static hipError_t launch_lds(const Buffers &b, const SweepScalars &sc, int block
 }
 
 hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s) {
-  const int R = rows_per_wave(sc.d);
-  const int groups = ((sc.n + R - 1) / R + 3) / 4;
-  const dim3 grid(groups * sc.nchunks), block(256);
-  if (sc.d > 4) return launch_lds<MODE_COUNT>(b, sc, (int)grid.x, s);
-  // d <= 4: the triangular sweep; sc.chunk / sc.rgroup give its tiles
+  const dim3 block(256);
+  // the triangular sweeps; sc.chunk / sc.rgroup give their tiles
   if (sc.chunk % 64 != 0 || sc.chunk > kTriMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0)
     return hipErrorInvalidValue;
   const dim3 tgrid(((sc.n + sc.rgroup - 1) / sc.rgroup) * sc.nchunks);
+  if (sc.d > 4) {
+    const size_t lds = (size_t)4 * kRowsLds * sc.d_pad * sizeof(float);
+    switch (coord_chunk(sc.d)) {
+#define DBK_TRI_LDS(DC)                                                                       \
+  case DC:                                                                                    \
+    if (emit_pairs)                                                                           \
+      hipLaunchKernelGGL((k_count_tri_lds<DC, kRowsLds, true>), tgrid, block, lds, s, b.soa,  \
+                         b.counts, b.pairs, b.st, sc);                                        \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_count_tri_lds<DC, kRowsLds, false>), tgrid, block, lds, s, b.soa, \
+                         b.counts, b.pairs, b.st, sc);                                        \
+    break;
+      DBK_TRI_LDS(8)
+      DBK_TRI_LDS(16)
+      DBK_TRI_LDS(32)
+      DBK_TRI_LDS(64)
+#undef DBK_TRI_LDS
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
 #define DBK_COUNT(D)                                                                          \
   if (emit_pairs)                                                                             \
     hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true>), tgrid, block, 0, s, b.soa,        \
@@ -406,7 +539,7 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
     case 2: DBK_COUNT(2)
     case 3: DBK_COUNT(3)
     case 4: DBK_COUNT(4)
-    default: return launch_lds<MODE_COUNT>(b, sc, (int)grid.x, s);
+    default: return hipErrorInvalidValue;
   }
 #undef DBK_COUNT
   return hipGetLastError();

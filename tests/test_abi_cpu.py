@@ -79,15 +79,15 @@ def test_workspace_size_layout():
     small = _lib.make_opts("onthefly", pair_capacity=1000)
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(small), ctypes.byref(out)) == 0
     assert out.value == base + 8 * 1024  # 1000 pairs, rounded up to 256 bytes
-    wide = _lib.make_opts("onthefly", "fp32")  # d > 4 in float32: no pair list
+    wide = _lib.make_opts("onthefly", "fp32")  # d > 4 in float32: pair list too
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(wide), ctypes.byref(out)) == 0
-    assert out.value < 32 * 100_096 * 4
+    assert 8 * 128 * 100_000 < out.value < 8 * 128 * 100_000 + 32 * 100_096 * 4
     plain = out.value
     # matrix cores (auto for 16 <= d <= 76): + two augmented copies (K = 32 here,
-    # 2 bytes each), 128 pairs and 64 band entries per point, 8 bytes each
+    # 2 bytes each) and 64 band entries per point, 8 bytes each
     mc = _lib.make_opts("onthefly", "auto")
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(mc), ctypes.byref(out)) == 0
-    extra = 2 * 100_096 * 32 * 2 + 8 * 128 * 100_000 + 8 * 64 * 100_000
+    extra = 2 * 100_096 * 32 * 2 + 8 * 64 * 100_000
     assert out.value - plain == extra
     big_d = _lib.make_opts("auto", "bf16")
     assert L.dbscan_workspace_size(1000, 77, ctypes.byref(big_d), ctypes.byref(out)) == _lib.DBSCAN_E_UNSUPPORTED

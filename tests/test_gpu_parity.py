@@ -243,6 +243,21 @@ def test_pair_list_overflow_falls_back(cap):
     assert st["pair_overflow"] == (1 if 0 < cap < half_edges else 0)
 
 
+@pytest.mark.parametrize("cap", [1, 0])
+def test_pair_list_wide_float32(cap):
+    """d > 4 in float32 (rows staged in LDS) records the pair list the same
+    way, and falls back to repeated tests when it overflows."""
+    w = wl.by_name("mix64d_300k_q50", n=6000)
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    gpu = run(w.points, w.eps, w.minpts, adjacency="onthefly", precision="fp32",
+              pair_capacity=cap, stats=True)
+    assert_same(gpu, ref, f"cap={cap}")
+    st = gpu[3]
+    half_edges = (int(ref[2].sum()) - w.n) // 2
+    assert half_edges > 0 and st["pairs_listed"] == half_edges
+    assert st["pair_overflow"] == (1 if cap == 1 else 0)
+
+
 # ------------------------------------------------------------ matrix cores
 PRECS = ("bf16", "fp16")
 
