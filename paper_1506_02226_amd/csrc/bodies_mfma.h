@@ -191,11 +191,18 @@ constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 // 2KS+1 chunks: the pitch is odd, so the 16 rows that one pass of a 16-byte
 // read touches fall in 16 distinct bank groups (no conflicts), and the
 // writes, which follow the global row-major order, stay nearly conflict-free.
+constexpr int kMfmaChunkTiles = 64;   // row tiles of 32 per work item, at most
+constexpr int kBandQueue = 128;       // band queue (pairs); appended 64 at a time
+
 template <int KS>
 struct MfmaLds {
   static constexpr int kPitch = 2 * KS + 1;
   uint4 atile[3][32 * kPitch];
-  int2 qbuf[4][2][kListQueue];
+  int2 qpair[4][kListQueue];
+  int2 qband[4][kBandQueue];
+  // row-side counts of the item's rows, two 16-bit counts per word (a row
+  // meets at most 256 columns in one item)
+  unsigned rowcnt[kMfmaChunkTiles * 32 / 2];
   unsigned long long xfer[5];
 };
 
@@ -213,7 +220,6 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   constexpr int K = KS * 16;
   constexpr int kPitch = MfmaLds<KS>::kPitch;
   V (*atile)[32 * kPitch] = reinterpret_cast<V (*)[32 * kPitch]>(lds.atile);
-  int2 (*qbuf)[2][kListQueue] = lds.qbuf;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = wave_uniform(tid >> 6);
@@ -255,8 +261,10 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   // flight, so the matrix-core work never waits on global memory
   __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
   int cnt[2] = {0, 0};
-  WaveQueue qp{qbuf[w][0], 0, kListDrain};
-  WaveQueue qb{qbuf[w][1], 0, kListDrain};
+  WaveQueue qp{lds.qpair[w], 0, kListDrain};
+  WaveQueue qb{lds.qband[w], 0, kBandQueue - 64};
+  const int row_first = chunk * sc.chunk * 32;  // rowcnt[k] covers rows row_first + 2k, +1
+  for (int k = tid; k < sc.chunk * 16; k += 256) lds.rowcnt[k] = 0u;  // before the first barrier
 
   // cooperative a-tile load: 32 rows x 2KS 16-byte chunks (coalesced).
   // Three LDS buffers: at the top of iteration t, tile t+1 (fetched into
@@ -320,7 +328,10 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
             // row side: lanes 0-31 share one row, lanes 32-63 another
             const uint64_t bm = __ballot(in);
             const uint32_t half = (uint32_t)(bm >> (lane & 32));
-            if ((lane & 31) == 0 && half != 0u) atomicAdd(counts + i, __popc(half));
+            if ((lane & 31) == 0 && half != 0u) {
+              const int k = i - row_first;
+              atomicAdd(&lds.rowcnt[k >> 1], (unsigned)__popc(half) << ((k & 1) * 16));
+            }
           }
           wq_push(qp, in && i > j, i, j);
           wq_drain_list(qp, pairs, sc.pair_cap, st, false);
@@ -347,6 +358,14 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   }
   wq_flush_block(qp, pairs, sc.pair_cap, &st->edges, &st->status, kStatusEdgeOverflow, lds.xfer);
   wq_flush_block(qb, band, sc.band_cap, &st->band_list, &st->status, kStatusBandOverflow, lds.xfer);
+  // row-side counts (wq_flush_block ends with a barrier)
+  for (int k = tid; k < sc.chunk * 16; k += 256) {
+    const unsigned v = lds.rowcnt[k];
+    if (v == 0u) continue;
+    const int i = row_first + 2 * k;
+    if ((v & 0xffffu) && i < sc.n) atomicAdd(counts + i, (int)(v & 0xffffu));
+    if ((v >> 16) && i + 1 < sc.n) atomicAdd(counts + i + 1, (int)(v >> 16));
+  }
   // lanes l and l+32 hold the same column
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -381,7 +400,7 @@ __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts
       pr = band[e];
       const bool both = ((unsigned)pr.x & kBandBoth) != 0u;
       pr.x = (int)((unsigned)pr.x & ~kBandBoth);
-      in = exact_within_mem(pts + (size_t)pr.x * d, 1, pts + (size_t)pr.y * d, 1, d, eps2);
+      in = exact_within_rows(pts + (size_t)pr.x * d, pts + (size_t)pr.y * d, d, eps2);
       if (in) {
         atomicAdd(counts + pr.y, 1);
         if (both) atomicAdd(counts + pr.x, 1);

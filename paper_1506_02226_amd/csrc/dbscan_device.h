@@ -85,6 +85,34 @@ __device__ __forceinline__ bool exact_within_mem(const float *a, int sa, const f
   return s <= eps2;
 }
 
+// Same, for two row-major rows of d floats: 16-byte loads when both rows are
+// 16-byte aligned and d is a multiple of 4 (same order of operations).
+__device__ __forceinline__ bool exact_within_rows(const float *a, const float *b, int d,
+                                                  double eps2) {
+#pragma clang fp contract(off)
+  if ((d & 3) == 0 && ((((uintptr_t)a) | ((uintptr_t)b)) & 15) == 0) {
+    const float4 *a4 = (const float4 *)a, *b4 = (const float4 *)b;
+    double s = 0.0;
+    for (int k = 0; k < (d >> 2); ++k) {
+      const float4 x = a4[k], y = b4[k];
+      double t = (double)x.x - (double)y.x;
+      double tt = t * t;
+      s = s + tt;
+      t = (double)x.y - (double)y.y;
+      tt = t * t;
+      s = s + tt;
+      t = (double)x.z - (double)y.z;
+      tt = t * t;
+      s = s + tt;
+      t = (double)x.w - (double)y.w;
+      tt = t * t;
+      s = s + tt;
+    }
+    return s <= eps2;
+  }
+  return exact_within_mem(a, 1, b, 1, d, eps2);
+}
+
 // float32 direct form; any evaluation order is covered by the band.
 template <int D>
 __device__ __forceinline__ float sq_dist32(const float (&a)[D], const float (&b)[D]) {
