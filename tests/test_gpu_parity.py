@@ -78,6 +78,22 @@ def test_ragged_random(n, d):
         assert_same(run(pts, eps, minpts, adjacency=mode), ref, f"n={n} d={d} {mode}")
 
 
+@pytest.mark.parametrize("d", [77, 300, 1024])
+def test_wide_float32(d):
+    """Dimensions beyond the matrix-core range run the float32 sweep with
+    rows staged in LDS (d up to the documented maximum of 1024)."""
+    rng = np.random.default_rng(d)
+    k = 6
+    centres = rng.uniform(0, 4, size=(k, d))
+    pts = centres[rng.integers(0, k, size=650)] + 0.05 * rng.standard_normal((650, d))
+    pts = np.concatenate([pts, rng.uniform(0, 4, size=(50, d))]).astype(np.float32)
+    eps = float(0.08 * np.sqrt(d))
+    ref = orc.dbscan(pts, eps, 4)
+    gpu = run(pts, eps, 4, stats=True)
+    assert gpu[3]["precision_used"] == "fp32"
+    assert_same(gpu, ref, f"d={d}")
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_integer_grid_ties(mode):
     """Every neighbour pair of a unit grid sits exactly at eps: all of them
