@@ -22,7 +22,7 @@ __device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const f
 // the 64-column blocks from the one holding its own rows onwards, so each
 // unordered pair is tested once.  Counts come from both sides of a test: the
 // row side as ballot popcounts (scalar registers), the column side as a
-// per-lane tally (the add-with-carry of the ballot bit) summed per block in
+// per-lane tally (taken only when a row's ballot is not empty) summed per block in
 // `colcnt` (LDS, sc.chunk entries) and added to counts[] at the end.  In the
 // diagonal 64x64 block every row visits all 64 columns itself, so there the
 // column tally is not taken, and only pairs below the diagonal are listed.
@@ -73,20 +73,15 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const float s = sq_dist32<D>(xr[r], xc);
-        uint64_t m, carry;
-        // m = ballot(s <= hi); tally += this lane's bit of m
-        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
-            "v_addc_co_u32_e64 %0, %2, %0, 0, %1"
-            : "+v"(tally), "=&s"(m), "=&s"(carry)
-            : "s"(sc.hi), "v"(s));
-        if (m != 0ull) {
+        const uint64_t m = __ballot(s <= sc.hi);
+        if (m != 0ull) {  // rare: the column tally and the row's count only then
           const uint64_t lo_m = __ballot(s <= sc.lo);
           uint64_t in = m;
           if (lo_m != m) {
             in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
                                   sc.eps2, st);
-            tally -= (uint32_t)(((m ^ in) >> lane) & 1ull);  // in is a subset of m
           }
+          tally += ((in >> lane) & 1ull) ? 1u : 0u;
           cnt[r] += __popcll(in);
           if (EMIT) {
             if (off) {

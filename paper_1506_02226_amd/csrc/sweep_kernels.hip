@@ -249,13 +249,8 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
       uint32_t tally = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        uint64_t m, carry;
-        // m = ballot(s <= hi); tally += this lane's bit of m
-        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
-            "v_addc_co_u32_e64 %0, %2, %0, 0, %1"
-            : "+v"(tally), "=&s"(m), "=&s"(carry)
-            : "s"(sc.hi), "v"(s[r]));
-        if (m != 0ull) {
+        const uint64_t m = __ballot(s[r] <= sc.hi);
+        if (m != 0ull) {  // rare: the column tally and the row's count only then
           const uint64_t lo_m = __ballot(s[r] <= sc.lo);
           uint64_t in = m;
           if (lo_m != m) {
@@ -265,8 +260,8 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
               ex = exact_within_mem(my_rows + r * dp, 1, soa + j, sc.n_pad, sc.d, sc.eps2);
             in = lo_m | __ballot(ex);
             if (lane == 0) atomicAdd(&st->band_pairs, (unsigned long long)__popcll(band));
-            tally -= (uint32_t)(((m ^ in) >> lane) & 1ull);  // in is a subset of m
           }
+          tally += ((in >> lane) & 1ull) ? 1u : 0u;
           cnt[r] += __popcll(in);
           if (EMIT) {
             if (off) {
