@@ -186,13 +186,16 @@ __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ 
 // R-row blocks from their own diagonal 64-column block on, row counts from
 // ballots, column counts from per-lane tallies summed in LDS, pair list
 // through wave queues), with the R rows of a wave staged in LDS (d_pad
-// floats each, read as broadcasts) and the coordinates taken DC at a time.
+// floats each, read as broadcasts), NB column blocks at a time and the
+// coordinates taken KC at a time (d_pad is a multiple of DC >= 8).
 template <int DC, int R, bool EMIT>
 __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__ soa,
                                                        int *__restrict__ counts,
                                                        int2 *__restrict__ pairs,
                                                        DevState *__restrict__ st,
                                                        SweepScalars sc) {
+  constexpr int NB = 4, KC = 8;
+  static_assert(DC % KC == 0, "coordinate chunk");
   extern __shared__ float lds_rows[];  // [4][R][d_pad]
   __shared__ int2 qbuf[4][kListQueue];
   __shared__ int colcnt[kTriMaxChunk];
@@ -224,57 +227,75 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
     int cnt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) cnt[r] = 0;
-    for (int cb = cs; cb < c1; cb += 64) {
-      const int j = cb + lane;
-      float s[R];
+    // NB column blocks (NB x 64 columns) at a time: each row coordinate read
+    // from LDS (a broadcast) serves NB tests per lane
+    for (int cg = cs; cg < c1; cg += NB * 64) {
+      float s[NB][R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[r] = 0.0f;
-      for (int kc = 0; kc < dp; kc += DC) {
-        float xc[DC];
+      for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int k = 0; k < DC; ++k) xc[k] = soa[(size_t)(kc + k) * sc.n_pad + j];
+        for (int r = 0; r < R; ++r) s[b][r] = 0.0f;
+      for (int kc = 0; kc < dp; kc += KC) {
+        float xc[NB][KC];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int jl = min(cg + b * 64 + lane, sc.n_pad - 1);  // blocks past c1 are not used
+#pragma unroll
+          for (int k = 0; k < KC; ++k) xc[b][k] = soa[(size_t)(kc + k) * sc.n_pad + jl];
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const float *xrow = my_rows + r * dp + kc;
-          float a = s[r];
+          float xr[KC];
 #pragma unroll
-          for (int k = 0; k < DC; ++k) {
-            const float t = xrow[k] - xc[k];
-            a = __builtin_fmaf(t, t, a);
-          }
-          s[r] = a;
-        }
-      }
-      const bool off = cb != diag;
-      uint32_t tally = 0;
+          for (int k = 0; k < KC; ++k) xr[k] = my_rows[r * dp + kc + k];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint64_t m = __ballot(s[r] <= sc.hi);
-        if (m != 0ull) {  // rare: the column tally and the row's count only then
-          const uint64_t lo_m = __ballot(s[r] <= sc.lo);
-          uint64_t in = m;
-          if (lo_m != m) {
-            const uint64_t band = m & ~lo_m;
-            bool ex = false;
-            if ((band >> lane) & 1ull)
-              ex = exact_within_mem(my_rows + r * dp, 1, soa + j, sc.n_pad, sc.d, sc.eps2);
-            in = lo_m | __ballot(ex);
-            if (lane == 0) atomicAdd(&st->band_pairs, (unsigned long long)__popcll(band));
-          }
-          tally += ((in >> lane) & 1ull) ? 1u : 0u;
-          cnt[r] += __popcll(in);
-          if (EMIT) {
-            if (off) {
-              wq_push(qu, (in >> lane) & 1ull, j, row0 + r);
-            } else {
-              const uint64_t e = in & below_mask(row0 + r, cb);
-              if (e != 0ull) wq_push(qu, (e >> lane) & 1ull, row0 + r, j);
+          for (int b = 0; b < NB; ++b) {
+            float a = s[b][r];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+              const float t = xr[k] - xc[b][k];
+              a = __builtin_fmaf(t, t, a);
             }
-            wq_drain_list(qu, pairs, sc.edge_cap, st, false);
+            s[b][r] = a;
           }
         }
       }
-      if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int cb = cg + b * 64;
+        if (cb >= c1) break;  // wave-uniform
+        const int j = cb + lane;
+        const bool off = cb != diag;
+        uint32_t tally = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint64_t m = __ballot(s[b][r] <= sc.hi);
+          if (m != 0ull) {  // rare: the column tally and the row's count only then
+            const uint64_t lo_m = __ballot(s[b][r] <= sc.lo);
+            uint64_t in = m;
+            if (lo_m != m) {
+              const uint64_t band = m & ~lo_m;
+              bool ex = false;
+              if ((band >> lane) & 1ull)
+                ex = exact_within_mem(my_rows + r * dp, 1, soa + j, sc.n_pad, sc.d, sc.eps2);
+              in = lo_m | __ballot(ex);
+              if (lane == 0) atomicAdd(&st->band_pairs, (unsigned long long)__popcll(band));
+            }
+            tally += ((in >> lane) & 1ull) ? 1u : 0u;
+            cnt[r] += __popcll(in);
+            if (EMIT) {
+              if (off) {
+                wq_push(qu, (in >> lane) & 1ull, j, row0 + r);
+              } else {
+                const uint64_t e = in & below_mask(row0 + r, cb);
+                if (e != 0ull) wq_push(qu, (e >> lane) & 1ull, row0 + r, j);
+              }
+              wq_drain_list(qu, pairs, sc.edge_cap, st, false);
+            }
+          }
+        }
+        if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
+      }
     }
     int mine = 0;
 #pragma unroll
