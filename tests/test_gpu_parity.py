@@ -12,6 +12,7 @@ torch = pytest.importorskip("torch")
 import paper_1506_02226_amd as pkg
 from oracle import c_oracle, dbscan_oracle as orc
 from paper_1506_02226_amd import workloads as wl
+from helpers import sampled_checks
 
 pytestmark = pytest.mark.gpu
 
@@ -193,35 +194,6 @@ def test_scaled_recipes_full_parity(name, n):
         assert_same(run(w.points, w.eps, w.minpts, adjacency=mode), ref, f"{name} {mode}")
 
 
-def _sampled_checks(w, gpu, rows):
-    """Exact per-row checks against the oracle at any size."""
-    lab, core, cnt = gpu[:3]
-    n = w.n
-    assert (core == (cnt >= w.minpts)).all()
-    ref_cnt = c_oracle.row_counts(w.points, w.eps, rows)
-    np.testing.assert_array_equal(cnt[rows], ref_cnt)
-    # canonical labels everywhere
-    nz = lab >= 0
-    assert (lab >= -1).all()
-    assert core[lab[nz]].all()
-    assert (lab[lab[nz]] == lab[nz]).all()
-    ci = np.flatnonzero(core)
-    assert (lab[ci] <= ci).all() and (lab[ci] >= 0).all()
-    # per sampled row: neighbours, their exact core flags, label rules
-    for i in rows[:4]:
-        nb = np.flatnonzero(c_oracle.row_neighbours(w.points, w.eps, int(i)))
-        nb_core = c_oracle.row_counts(w.points, w.eps, nb) >= w.minpts
-        np.testing.assert_array_equal(core[nb], nb_core)
-        core_nb = nb[nb_core]
-        if core[i]:
-            assert (lab[core_nb] == lab[i]).all()
-        elif core_nb.size:
-            assert lab[i] == lab[core_nb.min()]
-        else:
-            assert lab[i] == -1
-    assert n == len(lab)
-
-
 def test_blobs2d_200k_full_size():
     w = wl.blobs2d_200k(0)
     gpu = run(w.points, w.eps, w.minpts, stats=True)
@@ -229,7 +201,7 @@ def test_blobs2d_200k_full_size():
     rng = np.random.default_rng(0)
     rows = np.sort(rng.choice(w.n, 64, replace=False))
     rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:8]])
-    _sampled_checks(w, gpu, rows)
+    sampled_checks(w, gpu, rows)
     other = run(w.points, w.eps, w.minpts, adjacency="onthefly")
     for x, y in zip(gpu[:3], other):
         np.testing.assert_array_equal(x, y)
@@ -242,7 +214,7 @@ def test_aniso3d_2m_full_size():
     rng = np.random.default_rng(1)
     rows = np.sort(rng.choice(w.n, 16, replace=False))
     rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]])
-    _sampled_checks(w, gpu, rows)
+    sampled_checks(w, gpu, rows)
 
 
 @pytest.mark.parametrize("cap", [1, 100, 0])
@@ -349,7 +321,7 @@ def test_mix64d_full_size_all_forms():
         assert (gpu[2] >= 1).all()
         if rule == "q50":
             assert 0 < gpu[1].sum() < w.n
-        _sampled_checks(w, gpu, np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]]))
+        sampled_checks(w, gpu, np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]]))
 
 
 @pytest.mark.parametrize("prec", PRECS)

@@ -137,3 +137,32 @@ def test_served_jobs_arriving_while_others_run():
     alone = _host(pkg.fit(_gpu(big.points), big_eps, big_minpts))
     for a, b in zip(ob, alone):
         np.testing.assert_array_equal(a, b)
+
+
+def test_served_full_recipe_jobs():
+    """Jobs of the served workload itself (its recipe at full size, n up to
+    1.6e5) in one server: the small ones equal the oracle everywhere, the
+    large ones on sampled rows and in every invariant."""
+    from helpers import sampled_checks
+    small = [1, 10, 18, 21, 23]   # n <= 9,275: d = 2, 64, 3, 16, 64
+    large = [3, 9]                # n = 147,911 (d = 64), 158,412 (d = 3)
+    jobs = {j: wl.served_job(j) for j in small + large}
+    with pkg.Server(max_slots=16) as srv:
+        ids = {j: srv.submit(_gpu(w.points), w.eps, w.minpts) for j, w in jobs.items()}
+        sts = {j: srv.wait(i, timeout=300) for j, i in ids.items()}
+        outs = {j: _host(srv.outputs(i)) for j, i in ids.items()}
+    for j, st in sts.items():
+        assert st["state"] == pkg._lib.JOB_DONE and st["error"] == 0, (j, st)
+        assert st["fallback"] == 0, j
+    for j in small:
+        w = jobs[j]
+        ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+        for a, b in zip(outs[j], ref):
+            np.testing.assert_array_equal(a, np.asarray(b).astype(a.dtype), err_msg=f"job {j}")
+    rng = np.random.default_rng(7)
+    for j in large:
+        w = jobs[j]
+        lab, core, cnt = outs[j]
+        rows = np.sort(rng.choice(w.n, 24, replace=False))
+        rows = np.concatenate([rows, np.flatnonzero(~core)[:4]])
+        sampled_checks(w, (lab, core, cnt), rows)
