@@ -11,10 +11,11 @@ namespace dbk {
 // One wave takes 32 rows at a time (the "goal points" of Section IV-A.3,
 // wave-uniform values held in vector registers so that the subtractions issue
 // at the full rate) and the 64 lanes hold 64 columns.  Per row, one compare
-// gives the 64-bit ballot of the row's neighbours among the columns (its
-// popcount is the row's count, on the scalar unit), and the same compare's
-// result is shifted into a per-lane 32-bit word with an add-with-carry
-// (w = 2w + bit).  After the 32 rows, lane j holds the pairs (rows
+// gives the 64-bit ballot of the row's neighbours among the columns; only
+// when a ballot is not empty -- rare at these densities, and tested once per
+// group of 4 rows -- does its popcount go to the row's count (scalar unit)
+// and the lane set bit r of its 32-bit word.  After the 32 rows, lane j holds
+// the pairs (rows
 // row0..row0+31, column j); by symmetry that is row j's word for the columns
 // row0..row0+31, stored at adj[row0/32][j] -- a coalesced 256-byte store per
 // wave.  Bit b of adj[q][i] is the pair (i, 32q+b).  Padded rows and columns
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
                                                  uint32_t *__restrict__ adj,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
-  constexpr int R = 32;
+  constexpr int R = 32, G = 4;
   __shared__ int colcnt[kBitmaskMaxChunk];
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
@@ -77,23 +78,31 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
         for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
       }
       uint32_t word = 0;
+      // rows in groups of G: the common case (no neighbour among the 64
+      // columns for any of the G rows) costs one compare per row and one
+      // branch per group; the lane's bits and the row counts are set only
+      // in the rare case
 #pragma unroll
-      for (int r = R - 1; r >= 0; --r) {
-        const float s = sq_dist32<D>(xr[r], xc);
-        uint64_t m, carry;
-        // m = ballot(s <= hi); word = 2*word + (this lane's bit of m)
-        asm("v_cmp_ge_f32_e64 %1, %3, %4\n\t"
-            "v_addc_co_u32_e64 %0, %2, %0, %0, %1"
-            : "+v"(word), "=&s"(m), "=&s"(carry)
-            : "s"(sc.hi), "v"(s));
-        if (m != 0ull) {
-          const uint64_t lo_m = __ballot(s <= sc.lo);
-          uint64_t in = m;
-          if (lo_m != m) {
-            in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
+      for (int g = 0; g < R / G; ++g) {
+        float sg[G];
+        uint64_t mg[G], any = 0ull;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          sg[k] = sq_dist32<D>(xr[g * G + k], xc);
+          mg[k] = __ballot(sg[k] <= sc.hi);
+          any |= mg[k];
+        }
+        if (any == 0ull) continue;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+          const int r = g * G + k;
+          if (mg[k] == 0ull) continue;
+          const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
+          uint64_t in = mg[k];
+          if (lo_m != in)
+            in = recheck_band_soa(in & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
                                   sc.eps2, st);
-            word = (word & ~1u) | (uint32_t)((in >> lane) & 1ull);
-          }
+          word |= ((in >> lane) & 1ull) ? (1u << r) : 0u;
           cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
         }
       }

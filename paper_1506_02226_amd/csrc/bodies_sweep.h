@@ -70,17 +70,28 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       }
       const bool off = cb != diag;
       uint32_t tally = 0;
+      // rows in groups of 4: one branch per group in the common case
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float s = sq_dist32<D>(xr[r], xc);
-        const uint64_t m = __ballot(s <= sc.hi);
-        if (m != 0ull) {  // rare: the column tally and the row's count only then
-          const uint64_t lo_m = __ballot(s <= sc.lo);
+      for (int g = 0; g < R / 4; ++g) {
+        float sg[4];
+        uint64_t mg[4], any = 0ull;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          sg[k] = sq_dist32<D>(xr[g * 4 + k], xc);
+          mg[k] = __ballot(sg[k] <= sc.hi);
+          any |= mg[k];
+        }
+        if (any == 0ull) continue;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int r = g * 4 + k;
+          const uint64_t m = mg[k];
+          if (m == 0ull) continue;
+          const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
           uint64_t in = m;
-          if (lo_m != m) {
+          if (lo_m != m)
             in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
                                   sc.eps2, st);
-          }
           tally += ((in >> lane) & 1ull) ? 1u : 0u;
           cnt[r] += __popcll(in);
           if (EMIT) {
