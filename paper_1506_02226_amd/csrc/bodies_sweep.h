@@ -70,21 +70,22 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       }
       const bool off = cb != diag;
       uint32_t tally = 0;
-      // rows in groups of 4: one branch per group in the common case
+      // rows in groups of GR: one branch per group in the common case
+      constexpr int GR = R;
 #pragma unroll
-      for (int g = 0; g < R / 4; ++g) {
-        float sg[4];
-        uint64_t mg[4], any = 0ull;
+      for (int g = 0; g < R / GR; ++g) {
+        float sg[GR];
+        uint64_t mg[GR], any = 0ull;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          sg[k] = sq_dist32<D>(xr[g * 4 + k], xc);
+        for (int k = 0; k < GR; ++k) {
+          sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
           mg[k] = __ballot(sg[k] <= sc.hi);
           any |= mg[k];
         }
         if (any == 0ull) continue;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int r = g * 4 + k;
+        for (int k = 0; k < GR; ++k) {
+          const int r = g * GR + k;
           const uint64_t m = mg[k];
           if (m == 0ull) continue;
           const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
