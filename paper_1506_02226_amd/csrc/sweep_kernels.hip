@@ -267,9 +267,16 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
         const int j = cb + lane;
         const bool off = cb != diag;
         uint32_t tally = 0;
+        uint64_t mg[R], any = 0ull;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const uint64_t m = __ballot(s[b][r] <= sc.hi);
+          mg[r] = __ballot(s[b][r] <= sc.hi);
+          any |= mg[r];
+        }
+        if (any == 0ull) continue;  // one branch per block of R rows in the common case
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint64_t m = mg[r];
           if (m != 0ull) {  // rare: the column tally and the row's count only then
             const uint64_t lo_m = __ballot(s[b][r] <= sc.lo);
             uint64_t in = m;
