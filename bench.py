@@ -228,6 +228,7 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="blobs2d_200k")
     ap.add_argument("--adjacency", default="auto", choices=["auto", "bitmask", "onthefly"])
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
+    ap.add_argument("--order", default="auto", choices=["auto", "input", "spatial"])
     ap.add_argument("--cpu-sample", type=int, default=80_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -259,12 +260,13 @@ def main(argv=None) -> int:
     labels = torch.empty(n, dtype=torch.int32, device=dev)
     core = torch.empty(n, dtype=torch.uint8, device=dev)
     counts = torch.empty(n, dtype=torch.int32, device=dev)
-    ws_bytes = pkg.workspace_size(n, d, args.adjacency, args.precision)
+    ws_bytes = pkg.workspace_size(n, d, args.adjacency, args.precision, order=args.order)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     out = (labels, core, counts)
 
     # one checked call first: statistics (adjacency used, band pairs)
-    kw = dict(adjacency=args.adjacency, precision=args.precision, out=out, workspace=ws)
+    kw = dict(adjacency=args.adjacency, precision=args.precision, out=out, workspace=ws,
+              order=args.order)
     _, _, _, st = pkg.fit(x, w.eps, w.minpts, stats=True, **kw)
 
     if args.copy_probe:
@@ -328,7 +330,7 @@ def main(argv=None) -> int:
         "data": "synthetic",
         "config": {"workload": w.name, "n": n, "d": d, "eps": w.eps, "minpts": w.minpts,
                    "seed": w.meta.get("seed", 0), "adjacency": st["adjacency_used"],
-                   "precision": st["precision_used"]},
+                   "precision": st["precision_used"], "order": st["order_used"]},
         "points_per_s": round(n / (ms_step * 1e-3), 1),
         "phase_ms": {"step1": round(float(np.mean(s1)), 4), "step2": round(float(np.mean(s2)), 4),
                      "step3": round(float(np.mean(s3)), 4)},

@@ -68,6 +68,17 @@ extern "C" {
 #define DBSCAN_ADJ_BITMASK 1  /* one bit per ordered pair, kept in device memory */
 #define DBSCAN_ADJ_ONTHEFLY 2 /* nothing stored; step 3 repeats the epsilon tests */
 
+/* Order in which the rows are processed (results are always returned in the
+ * caller's order and are identical either way). */
+#define DBSCAN_ORDER_AUTO 0    /* spatial for the float32 forms with d <= 4, else input */
+#define DBSCAN_ORDER_INPUT 1   /* the caller's order */
+#define DBSCAN_ORDER_SPATIAL 2 /* rows permuted on the device by a Morton key of their
+                                  coordinates (quantised over the bounding box), so that
+                                  neighbours sit at nearby indices: the sweeps meet their
+                                  rare neighbour branch far less often and the bitmask's
+                                  set bits gather near its diagonal.  float32 forms with
+                                  d <= 4 only (else DBSCAN_E_UNSUPPORTED). */
+
 /* Arithmetic of the epsilon-test filter (the decision is always float64-exact). */
 #define DBSCAN_PREC_AUTO 0 /* FP16 matrix cores for 16 <= d <= 76, else float32 */
 #define DBSCAN_PREC_FP32 1 /* float32 direct form (x_i - x_j)^2 summed */
@@ -103,6 +114,8 @@ typedef struct dbscan_opts {
                                  pair-test kernel, without staging or the float64
                                  band pass), so the caller can time the kernels of
                                  a call it does not wait for. */
+  int32_t order;              /* DBSCAN_ORDER_* (0 = auto) */
+  int32_t reserved;           /* must be 0 */
 } dbscan_opts;
 
 typedef struct dbscan_stats {
@@ -131,6 +144,8 @@ typedef struct dbscan_stats {
                              once, both orders inside 64x64 diagonal blocks)
                              and for the matrix-core tiles (256x256 diagonal
                              zones) */
+  int32_t order_used;     /* DBSCAN_ORDER_INPUT or DBSCAN_ORDER_SPATIAL */
+  int32_t reserved;
 } dbscan_stats;
 
 /*

@@ -23,8 +23,10 @@ DBSCAN_E_UNSUPPORTED = -1002
 
 ADJ = {"auto": 0, "bitmask": 1, "onthefly": 2}
 PREC = {"auto": 0, "fp32": 1, "bf16": 2, "fp16": 3}
+ORDER = {"auto": 0, "input": 1, "spatial": 2}
 ADJ_NAMES = {v: k for k, v in ADJ.items()}
 PREC_NAMES = {v: k for k, v in PREC.items()}
+ORDER_NAMES = {v: k for k, v in ORDER.items()}
 
 # Every symbol include/dbscan.h declares.
 EXPORTS = (
@@ -56,6 +58,8 @@ class Opts(ctypes.Structure):
         ("pair_capacity", ctypes.c_uint64),
         ("band_capacity", ctypes.c_uint64),
         ("events", ctypes.c_void_p),
+        ("order", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -79,12 +83,15 @@ class Stats(ctypes.Structure):
         ("filter_fallback", ctypes.c_int32),
         ("ms_sweep1", ctypes.c_float),
         ("sweep1_tests", ctypes.c_int64),
+        ("order_used", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         d = {name: getattr(self, name) for name, _ in self._fields_}
         d["adjacency_used"] = ADJ_NAMES.get(d["adjacency_used"], d["adjacency_used"])
         d["precision_used"] = PREC_NAMES.get(d["precision_used"], d["precision_used"])
+        d["order_used"] = ORDER_NAMES.get(d["order_used"], d["order_used"])
         return d
 
 
@@ -196,7 +203,8 @@ def load(path: str | None = None):
 
 def make_opts(adjacency: str = "auto", precision: str = "auto", band_rel: float = 0.0,
               bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0,
-              events: int = 0, pair_capacity: int = 0, band_capacity: int = 0) -> Opts:
+              events: int = 0, pair_capacity: int = 0, band_capacity: int = 0,
+              order: str = "auto") -> Opts:
     return Opts(ADJ[adjacency], PREC[precision], float(band_rel), int(bitmask_limit),
                 int(workspace) or None, int(workspace_bytes), int(pair_capacity),
-                int(band_capacity), int(events) or None)
+                int(band_capacity), int(events) or None, ORDER[order], 0)

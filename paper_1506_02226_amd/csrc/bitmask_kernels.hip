@@ -135,11 +135,16 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 //    neighbour below it (atomicMin on jstar[i], then the row stops looking).
 // A non-core point's core neighbours above it are found by those rows, so
 // after the pass jstar[v] is the lowest-index core neighbour of every
-// non-core v.
+// non-core v.  With a spatial order (ORDERED) the index that counts is the
+// caller's, okey[j]: jstar takes okey values, and a non-core row takes the
+// smallest okey over all its core neighbours below it instead of stopping
+// at the first.
+template <bool ORDERED>
 __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restrict__ adj,
                                                        const uint32_t *__restrict__ corebits,
                                                        int *__restrict__ parent,
                                                        int *__restrict__ jstar,
+                                                       const int *__restrict__ okey,
                                                        SweepScalars p) {
   __shared__ int2 qbuf[4][128];
   const int lane = lane_id();
@@ -151,6 +156,8 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   const bool valid = i < p.n;
   const bool is_core = valid && ((corebits[i >> 5] >> (i & 31)) & 1u);
   bool seek = valid && !is_core;
+  int best = kNoNeighbour;                               // ORDERED, non-core rows
+  const int my_key = (ORDERED && valid) ? okey[i] : i;  // key of row i in jstar
   const int qi = i >> 5;
   const int q0 = chunk * p.chunk;
   const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 32 + 1);  // lower triangle
@@ -175,9 +182,12 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
       if (__ballot(word != 0u) == 0ull) continue;
       const uint32_t cw = corebits[q];  // core flags of the columns 32q..32q+31
       if (!is_core) {
-        // the first core neighbour of a non-core row, in ascending order
-        const uint32_t hit = word & cw;
-        if (seek && hit != 0u) {
+        uint32_t hit = word & cw;
+        if (ORDERED) {
+          // the smallest caller index among the core neighbours
+          for (; hit != 0u; hit &= hit - 1u) best = min(best, okey[q * 32 + __builtin_ctz(hit)]);
+        } else if (seek && hit != 0u) {
+          // the first core neighbour of a non-core row, in ascending order
           atomicMin(jstar + i, q * 32 + __builtin_ctz(hit));
           seek = false;
         }
@@ -189,12 +199,13 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
         word &= word - 1u;
         const int j = q * 32 + b;
         const bool cj = (cw >> b) & 1u;
-        if (has && is_core && !cj) atomicMin(jstar + j, i);
+        if (has && is_core && !cj) atomicMin(jstar + j, my_key);
         wq_push(qu, has && is_core && cj, i, j);
         wq_drain_union(qu, parent, false);
       }
     }
   }
+  if (ORDERED && best != kNoNeighbour) atomicMin(jstar + i, best);
   wq_drain_union(qu, parent, true);
 }
 
@@ -216,8 +227,12 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
-  hipLaunchKernelGGL(k_merge_bitmask, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                     (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, sc);
+  if (b.okey)
+    hipLaunchKernelGGL(k_merge_bitmask<true>, dim3(groups * sc.nchunks), dim3(256), 0, s,
+                       (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, b.okey, sc);
+  else
+    hipLaunchKernelGGL(k_merge_bitmask<false>, dim3(groups * sc.nchunks), dim3(256), 0, s,
+                       (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, b.okey, sc);
   return hipGetLastError();
 }
 

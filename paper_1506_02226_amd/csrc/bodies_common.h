@@ -8,19 +8,22 @@
 
 namespace dbk {
 
-// soa[k][i] = points[i][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n;
-// flags non-finite input.
+// soa[k][i] = points[p][k] for k < d, 0 for d <= k < d_pad, NaN for i >= n,
+// where p = perm[i] (the spatial order) or i without one; flags non-finite
+// input.
 __device__ __forceinline__ void stage_soa_body(const float *__restrict__ pts, int n, int d,
                                                int n_pad, int d_pad, float *__restrict__ soa,
-                                               DevState *st, int bid) {
+                                               DevState *st, int bid,
+                                               const int *__restrict__ perm = nullptr) {
   const int i = bid * 256 + (int)threadIdx.x;
   if (i >= n_pad) return;
   bool bad = false;
   const float qnan = __builtin_nanf("");
+  const size_t src = (perm && i < n) ? (size_t)perm[i] : (size_t)i;
   for (int k = 0; k < d_pad; ++k) {
     float v;
     if (i < n) {
-      v = (k < d) ? pts[(size_t)i * d + k] : 0.0f;
+      v = (k < d) ? pts[src * d + k] : 0.0f;
       bad |= !__builtin_isfinite(v);
     } else {
       v = qnan;
@@ -31,28 +34,49 @@ __device__ __forceinline__ void stage_soa_body(const float *__restrict__ pts, in
 }
 
 // Clears counts, parent = identity, jstar = none; with `soa`, also stages the
-// coordinates (stage_soa_body).
+// coordinates (stage_soa_body).  With a spatial order `perm` (staged index ->
+// caller's index) it also fills its inverse and clears the per-root lowest
+// caller index used by the labels.
 __device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n, int d, int n_pad,
                                            int d_pad, float *__restrict__ soa,
                                            int *__restrict__ counts, int *__restrict__ parent,
-                                           int *__restrict__ jstar, DevState *st, int bid) {
-  if (soa) stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, bid);
+                                           int *__restrict__ jstar, DevState *st, int bid,
+                                           const int *__restrict__ perm = nullptr,
+                                           int *__restrict__ inv = nullptr,
+                                           int *__restrict__ rootmin = nullptr) {
+  if (soa) stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, bid, perm);
   const int i = bid * 256 + (int)threadIdx.x;
   if (i < n) {
     counts[i] = 0;
     parent[i] = i;
     jstar[i] = kNoNeighbour;
+    if (perm) {
+      inv[perm[i]] = i;
+      rootmin[i] = kNoNeighbour;
+    }
   }
 }
 
 // ------------------------------------------------------------- core flags
+// corebits in the staged order; core[] (and, with a spatial order, the
+// counts) written in the caller's order.
 __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n, int n_pad,
                                           int minpts, uint8_t *__restrict__ core,
-                                          uint32_t *__restrict__ corebits, DevState *st, int bid) {
+                                          uint32_t *__restrict__ corebits, DevState *st, int bid,
+                                          const int *__restrict__ perm = nullptr,
+                                          int *__restrict__ counts_out = nullptr) {
   const int i = bid * 256 + (int)threadIdx.x;
   if (i >= n_pad) return;  // n_pad is a multiple of 64: whole waves
   const bool c = i < n && counts[i] >= minpts;
-  if (i < n) core[i] = c ? 1 : 0;
+  if (i < n) {
+    if (perm) {
+      const int o = perm[i];
+      core[o] = c ? 1 : 0;
+      counts_out[o] = counts[i];
+    } else {
+      core[i] = c ? 1 : 0;
+    }
+  }
   const uint64_t m = __ballot(c);
   const int lane = lane_id();
   if (lane == 0) {
@@ -64,15 +88,17 @@ __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n,
 
 // --------------------------------------------- merge + border from the list
 // Every neighbour pair (a, b), b < a, found by step 1: core-core pairs are
-// joined in the union-find; a non-core end takes the smaller index of its
-// core neighbours (atomicMin), which after all pairs is its lowest-index core
+// joined in the union-find; a non-core end takes the smaller caller index
+// (okey[], or the index itself without a spatial order) of its core
+// neighbours (atomicMin), which after all pairs is its lowest-index core
 // neighbour.  This block handles pairs [e_begin, e_end).
 __device__ __forceinline__ void merge_pairs_range(const int2 *__restrict__ pairs,
                                                   const uint32_t *__restrict__ corebits,
                                                   int *__restrict__ parent,
                                                   int *__restrict__ jstar,
                                                   unsigned long long e_begin,
-                                                  unsigned long long e_end) {
+                                                  unsigned long long e_end,
+                                                  const int *__restrict__ okey = nullptr) {
   for (unsigned long long e = e_begin + threadIdx.x; e < e_end; e += 256) {
     const int2 pr = pairs[e];
     const bool ca = (corebits[pr.x >> 5] >> (pr.x & 31)) & 1u;
@@ -80,28 +106,52 @@ __device__ __forceinline__ void merge_pairs_range(const int2 *__restrict__ pairs
     if (ca && cb)
       uf_union(parent, pr.x, pr.y);
     else if (ca)
-      atomicMin(jstar + pr.y, pr.x);
+      atomicMin(jstar + pr.y, okey ? okey[pr.x] : pr.x);
     else if (cb)
-      atomicMin(jstar + pr.x, pr.y);
+      atomicMin(jstar + pr.x, okey ? okey[pr.y] : pr.y);
   }
 }
 
 // ------------------------------------------------------------------ labels
-__device__ __forceinline__ void labels_body(int n, const uint8_t *__restrict__ core,
+// Without a spatial order a tree's root is the lowest index of its component
+// (the union-find hooks larger roots under smaller ones), so it is the label.
+// With one (perm: staged index -> caller's index), the label of a component
+// is the lowest caller index of its core points, gathered per root first by
+// rootmin_body; jstar then holds caller indices and inv maps them back.
+__device__ __forceinline__ void rootmin_body(int n, const uint32_t *__restrict__ corebits,
+                                             int *__restrict__ parent,
+                                             const int *__restrict__ perm,
+                                             int *__restrict__ rootmin, int bid) {
+  const int i = bid * 256 + (int)threadIdx.x;
+  if (i >= n || !((corebits[i >> 5] >> (i & 31)) & 1u)) return;
+  atomicMin(rootmin + uf_find(parent, i), perm[i]);
+}
+
+__device__ __forceinline__ void labels_body(int n, const uint32_t *__restrict__ corebits,
                                             const int *__restrict__ jstar, int *__restrict__ parent,
-                                            int *__restrict__ labels, const DevState *st, int bid) {
+                                            int *__restrict__ labels, const DevState *st, int bid,
+                                            const int *__restrict__ perm = nullptr,
+                                            const int *__restrict__ inv = nullptr,
+                                            const int *__restrict__ rootmin = nullptr) {
   const int i = bid * 256 + (int)threadIdx.x;
   if (i >= n) return;
+  const int o = perm ? perm[i] : i;
   if (st->status & kStatusNonFinite) {
-    labels[i] = -2;
+    labels[o] = -2;
     return;
   }
-  if (core[i]) {
-    labels[i] = uf_find(parent, i);
+  int root;
+  if ((corebits[i >> 5] >> (i & 31)) & 1u) {
+    root = uf_find(parent, i);
   } else {
     const int j = jstar[i];
-    labels[i] = (j == kNoNeighbour) ? -1 : uf_find(parent, j);
+    if (j == kNoNeighbour) {
+      labels[o] = -1;
+      return;
+    }
+    root = uf_find(parent, perm ? inv[j] : j);
   }
+  labels[o] = perm ? rootmin[root] : root;
 }
 
 }  // namespace dbk

@@ -20,32 +20,39 @@ __global__ void k_reset_state(DevState *st) {
     st->max_norm = 0;
     st->thr[0] = 0.0f;
     st->thr[1] = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+      st->box_lo[k] = ~0u;
+      st->box_hi[k] = 0u;
+    }
   }
 }
 
 __global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, int d_pad,
                         float *__restrict__ soa, int *__restrict__ counts,
-                        int *__restrict__ parent, int *__restrict__ jstar, DevState *st) {
-  stage_body(pts, n, d, n_pad, d_pad, soa, counts, parent, jstar, st, blockIdx.x);
+                        int *__restrict__ parent, int *__restrict__ jstar, DevState *st,
+                        const int *__restrict__ perm, int *__restrict__ inv,
+                        int *__restrict__ rootmin) {
+  stage_body(pts, n, d, n_pad, d_pad, soa, counts, parent, jstar, st, blockIdx.x, perm, inv,
+             rootmin);
 }
 
 // ------------------------------------------------------------- core flags
 __global__ void k_core(const int *__restrict__ counts, int n, int n_pad, int minpts,
                        uint8_t *__restrict__ core, uint32_t *__restrict__ corebits,
-                       DevState *st) {
-  core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x);
+                       DevState *st, const int *__restrict__ perm, int *__restrict__ counts_out) {
+  core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x, perm, counts_out);
 }
 
 // Non-core rows into a list (any order) for the border pass that repeats the
 // epsilon tests.  With `only_on_overflow` it runs only when the pair list
 // overflowed (otherwise the pair list serves the border points).
-__global__ void k_compact_noncore(const uint8_t *__restrict__ core, int n, int *__restrict__ list,
-                                  DevState *st, int only_on_overflow) {
+__global__ void k_compact_noncore(const uint32_t *__restrict__ corebits, int n,
+                                  int *__restrict__ list, DevState *st, int only_on_overflow) {
   if (only_on_overflow && !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED,
                                               __HIP_MEMORY_SCOPE_AGENT) & kStatusEdgeOverflow))
     return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool nc = i < n && core[i] == 0;
+  const bool nc = i < n && !((corebits[i >> 5] >> (i & 31)) & 1u);
   const uint64_t m = __ballot(nc);
   if (m == 0ull) return;
   const int lane = lane_id();
@@ -61,7 +68,7 @@ __global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pai
                                                     const uint32_t *__restrict__ corebits,
                                                     int *__restrict__ parent,
                                                     int *__restrict__ jstar, DevState *st,
-                                                    long long cap) {
+                                                    long long cap, const int *__restrict__ okey) {
   const unsigned status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (status & kStatusEdgeOverflow) return;
   unsigned long long total =
@@ -70,13 +77,20 @@ __global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pai
   const unsigned long long per = (total + gridDim.x - 1) / gridDim.x;
   const unsigned long long b = (unsigned long long)blockIdx.x * per;
   const unsigned long long e = b + per < total ? b + per : total;
-  merge_pairs_range(pairs, corebits, parent, jstar, b, e);
+  merge_pairs_range(pairs, corebits, parent, jstar, b, e, okey);
 }
 
 // ------------------------------------------------------------------ labels
-__global__ void k_labels(int n, const uint8_t *__restrict__ core, const int *__restrict__ jstar,
-                         int *__restrict__ parent, int *__restrict__ labels, const DevState *st) {
-  labels_body(n, core, jstar, parent, labels, st, blockIdx.x);
+__global__ void k_rootmin(int n, const uint32_t *__restrict__ corebits, int *__restrict__ parent,
+                          const int *__restrict__ perm, int *__restrict__ rootmin) {
+  rootmin_body(n, corebits, parent, perm, rootmin, blockIdx.x);
+}
+
+__global__ void k_labels(int n, const uint32_t *__restrict__ corebits,
+                         const int *__restrict__ jstar, int *__restrict__ parent,
+                         int *__restrict__ labels, const DevState *st, const int *__restrict__ perm,
+                         const int *__restrict__ inv, const int *__restrict__ rootmin) {
+  labels_body(n, corebits, jstar, parent, labels, st, blockIdx.x, perm, inv, rootmin);
 }
 
 // ----------------------------------------------------- filter fallback
@@ -105,29 +119,30 @@ hipError_t run_reset(DevState *st, hipStream_t s) {
 }
 
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
-                     int *parent, int *jstar, DevState *st, hipStream_t s) {
+                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s) {
   hipLaunchKernelGGL(k_stage, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, n, d, n_pad, d_pad,
-                     soa, counts, parent, jstar, st);
+                     soa, counts, parent, jstar, st, ord.perm, ord.inv, ord.rootmin);
   return hipGetLastError();
 }
 
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
-                    uint32_t *corebits, DevState *st, hipStream_t s) {
+                    uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
+                    hipStream_t s) {
   hipLaunchKernelGGL(k_core, dim3((n_pad + 255) / 256), dim3(256), 0, s, counts, n, n_pad, minpts,
-                     core, corebits, st);
+                     core, corebits, st, ord.perm, counts_out);
   return hipGetLastError();
 }
 
-hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
+hipError_t run_compact_noncore(const uint32_t *corebits, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s) {
-  hipLaunchKernelGGL(k_compact_noncore, dim3((n + 255) / 256), dim3(256), 0, s, core, n, list, st,
-                     only_on_overflow ? 1 : 0);
+  hipLaunchKernelGGL(k_compact_noncore, dim3((n + 255) / 256), dim3(256), 0, s, corebits, n, list,
+                     st, only_on_overflow ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s) {
   hipLaunchKernelGGL(k_merge_list, dim3(2048), dim3(256), 0, s, b.pairs, b.corebits, b.parent,
-                     b.jstar, b.st, cap);
+                     b.jstar, b.st, cap, b.okey);
   return hipGetLastError();
 }
 
@@ -138,10 +153,13 @@ hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_
   return hipGetLastError();
 }
 
-hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
-                      const DevState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_labels, dim3((n + 255) / 256), dim3(256), 0, s, n, core, jstar, parent,
-                     labels, st);
+hipError_t run_labels(int n, const uint32_t *corebits, const int *jstar, int *parent, int *labels,
+                      const DevState *st, const Order &ord, hipStream_t s) {
+  if (ord.perm)
+    hipLaunchKernelGGL(k_rootmin, dim3((n + 255) / 256), dim3(256), 0, s, n, corebits, parent,
+                       ord.perm, ord.rootmin);
+  hipLaunchKernelGGL(k_labels, dim3((n + 255) / 256), dim3(256), 0, s, n, corebits, jstar, parent,
+                     labels, st, ord.perm, ord.inv, ord.rootmin);
   return hipGetLastError();
 }
 

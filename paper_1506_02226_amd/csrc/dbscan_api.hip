@@ -30,9 +30,14 @@ struct Layout {
   int32_t d_pad = 0;
   int adjacency = DBSCAN_ADJ_ONTHEFLY;
   int precision = DBSCAN_PREC_FP32;
+  int order = DBSCAN_ORDER_INPUT;
   uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
            off_list = 0, off_adj = 0, off_pairs = 0, off_aaug = 0, off_baug = 0, off_band = 0,
            total = 0;
+  // spatial order: sort keys and values (two buffers each), digit histograms,
+  // the inverse permutation, staged-order counts and per-root label minima
+  uint64_t off_keys[2] = {0, 0}, off_vals[2] = {0, 0}, off_hist = 0, off_inv = 0,
+           off_counts = 0, off_rootmin = 0;
   int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4 or matrix cores)
   int64_t band_cap = 0;  // band-list entries (matrix cores)
   int mfma_k = 0;        // contraction length of the matrix-core filter
@@ -71,6 +76,18 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   } else {
     return DBSCAN_E_INVAL;
   }
+  const int req_order = o ? o->order : DBSCAN_ORDER_AUTO;
+  const bool order_ok = d <= 4 && !mfma;
+  if (o && o->reserved != 0) return DBSCAN_E_INVAL;
+  if (req_order == DBSCAN_ORDER_AUTO)
+    L->order = order_ok ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
+  else if (req_order == DBSCAN_ORDER_INPUT)
+    L->order = DBSCAN_ORDER_INPUT;
+  else if (req_order == DBSCAN_ORDER_SPATIAL) {
+    if (!order_ok) return DBSCAN_E_UNSUPPORTED;
+    L->order = DBSCAN_ORDER_SPATIAL;
+  } else
+    return DBSCAN_E_INVAL;
   uint64_t off = 0;
   auto take = [&](uint64_t bytes) {
     const uint64_t at = off;
@@ -96,6 +113,16 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     const uint64_t req = (o && o->band_capacity) ? o->band_capacity : (uint64_t)kBandPerPoint * n;
     L->band_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
     L->off_band = take((uint64_t)L->band_cap * 8);
+  }
+  if (L->order == DBSCAN_ORDER_SPATIAL) {
+    for (int k = 0; k < 2; ++k) {
+      L->off_keys[k] = take((uint64_t)L->n_pad * 4);
+      L->off_vals[k] = take((uint64_t)L->n_pad * 4);
+    }
+    L->off_hist = take((uint64_t)dbk::order_hist_entries(n) * 4);
+    L->off_inv = take((uint64_t)L->n_pad * 4);
+    L->off_counts = take((uint64_t)L->n_pad * 4);
+    L->off_rootmin = take((uint64_t)L->n_pad * 4);
   }
   L->total = off;
   return DBSCAN_OK;
@@ -320,9 +347,25 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   };
 
   step(dbk::run_reset(st, s));
+  // spatial order: the permutation first, then the staging gathers through it
+  // and the kernels count into a staged-order array (scattered back by the
+  // core-flag pass)
+  dbk::Order ord{nullptr, nullptr, nullptr};
+  int *counts_k = counts;
+  if (L.order == DBSCAN_ORDER_SPATIAL) {
+    unsigned *keys[2] = {(unsigned *)(ws + L.off_keys[0]), (unsigned *)(ws + L.off_keys[1])};
+    int *vals[2] = {(int *)(ws + L.off_vals[0]), (int *)(ws + L.off_vals[1])};
+    int *perm = nullptr;
+    step(dbk::run_spatial_order(points, ni, d, keys, vals, (int *)(ws + L.off_hist), st, &perm,
+                                s));
+    ord.perm = perm;
+    ord.inv = (int *)(ws + L.off_inv);
+    ord.rootmin = (int *)(ws + L.off_rootmin);
+    counts_k = (int *)(ws + L.off_counts);
+  }
   // the matrix-core path stages the float32 coordinates only if it falls back
-  step(dbk::run_stage(points, ni, d, npad, L.d_pad, mfma ? nullptr : soa, counts, parent, jstar,
-                      st, s));
+  step(dbk::run_stage(points, ni, d, npad, L.d_pad, mfma ? nullptr : soa, counts_k, parent, jstar,
+                      st, ord, s));
   const double band_rel = (opts && opts->band_rel > 0.0) ? opts->band_rel : kDefaultBandRel;
   if (mfma) {
     step(dbk::run_mfma_prep(points, ni, d, npad, L.precision, a_aug, b_aug, st, s));
@@ -332,7 +375,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
 
   dbk::Buffers bufs{};
   bufs.soa = soa;
-  bufs.counts = counts;
+  bufs.counts = counts_k;
+  bufs.okey = ord.perm;
   bufs.corebits = corebits;
   bufs.parent = parent;
   bufs.jstar = jstar;
@@ -392,7 +436,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   }
   mark(1);
   // ---- step 2: core flags
-  step(dbk::run_core(counts, ni, npad, minpts, core, corebits, st, s));
+  step(dbk::run_core(counts_k, ni, npad, minpts, core, corebits, st, ord, counts, s));
   mark(2);
   // ---- step 3: merge (union-find over core-core neighbour pairs) and border
   // points (lowest-index core neighbour)
@@ -417,14 +461,14 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     f3.flags = dbk::kOnlyOnOverflow;
     b3.flags = dbk::kOnlyOnOverflow;
     step(dbk::run_union(bufs, f3, s));
-    step(dbk::run_compact_noncore(core, ni, list, st, true, s));
+    step(dbk::run_compact_noncore(corebits, ni, list, st, true, s));
     step(dbk::run_border(bufs, b3, s));
   } else {
     step(dbk::run_union(bufs, sc, s));
-    step(dbk::run_compact_noncore(core, ni, list, st, false, s));
+    step(dbk::run_compact_noncore(corebits, ni, list, st, false, s));
     step(dbk::run_border(bufs, b3, s));
   }
-  step(dbk::run_labels(ni, core, jstar, parent, labels, st, s));
+  step(dbk::run_labels(ni, corebits, jstar, parent, labels, st, ord, s));
   mark(3);
 
   dbk::DevState hst{};
@@ -453,6 +497,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   for (auto &x : ev) (void)hipEventDestroy(x);
   stats->adjacency_used = L.adjacency;
   stats->precision_used = L.precision;
+  stats->order_used = L.order;
   stats->pairs_tested = (int64_t)n * (int64_t)n;
   stats->pairs_rechecked = (int64_t)hst.band_pairs;
   stats->core_points = (int64_t)hst.core_points;

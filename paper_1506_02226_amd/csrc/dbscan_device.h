@@ -36,6 +36,7 @@ struct DevState {
   unsigned long long max_norm;     // bit pattern of max |x_i| (float64, >= 0)
   float thr[2];                    // matrix-core filter thresholds (in, out)
   unsigned long long reserved[2];
+  unsigned int box_lo[4], box_hi[4];  // bounding box of the input (order-preserving bits)
 };
 
 constexpr int kNoNeighbour = 0x7fffffff;

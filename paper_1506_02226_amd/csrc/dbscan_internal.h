@@ -17,11 +17,24 @@ struct Buffers {
   int *parent;         // [n_pad] union-find forest
   int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
   const int *list;     // [n_pad] compacted non-core rows
-  void *adjT;          // [n_pad/16][n_pad] uint16 bitmask adjacency (bitmask form only)
+  void *adjT;          // [n_pad/32][n_pad] uint32 bitmask adjacency (bitmask form only)
   int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
   int2 *band;          // [band_cap] pairs the matrix-core filter leaves undecided
   DevState *st;
+  const int *okey;     // [n] caller's index of each staged row (spatial order), or null
 };
+
+// Spatial order of one call (all null when the rows keep the caller's order).
+struct Order {
+  const int *perm;  // [n] staged row -> caller's index
+  int *inv;         // [n] caller's index -> staged row
+  int *rootmin;     // [n] lowest caller index of the core points under each root
+};
+
+// Bits per coordinate of the spatial-order key (d <= 4; at most 32 in all).
+__host__ __device__ inline int order_bits_per_coord(int d) {
+  return d == 1 ? 24 : (d == 2 ? 16 : (d == 3 ? 10 : 8));
+}
 
 // Scalars of one sweep (passed by value; SGPRs in the kernels).
 struct SweepScalars {
@@ -57,15 +70,19 @@ int rows_per_wave(int d);
 int coord_chunk(int d);
 
 hipError_t run_reset(DevState *st, hipStream_t s);
+long long order_hist_entries(long long n);
+hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], int *vals[2],
+                             int *hist, DevState *st, int **perm, hipStream_t s);
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
-                     int *parent, int *jstar, DevState *st, hipStream_t s);
+                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s);
 hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s);
 hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
-                    uint32_t *corebits, DevState *st, hipStream_t s);
-hipError_t run_compact_noncore(const uint8_t *core, int n, int *list, DevState *st,
+                    uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
+                    hipStream_t s);
+hipError_t run_compact_noncore(const uint32_t *corebits, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
 hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_pad, float *soa,
@@ -81,7 +98,7 @@ hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b
 hipError_t run_recheck_band(const float *pts, int d, const Buffers &b, double eps2,
                             long long band_cap, long long pair_cap, hipStream_t s);
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
-hipError_t run_labels(int n, const uint8_t *core, const int *jstar, int *parent, int *labels,
-                      const DevState *st, hipStream_t s);
+hipError_t run_labels(int n, const uint32_t *corebits, const int *jstar, int *parent, int *labels,
+                      const DevState *st, const Order &ord, hipStream_t s);
 
 }  // namespace dbk

@@ -136,7 +136,7 @@ __device__ __forceinline__ void run_task(const JobDesc &jd, int phase, int idx, 
       break;
     }
     case kPhLabels:
-      labels_body(jd.n, jd.core, jd.jstar, jd.parent, jd.labels, jd.st, idx);
+      labels_body(jd.n, jd.corebits, jd.jstar, jd.parent, jd.labels, jd.st, idx);
       break;
     default:
       break;

@@ -104,12 +104,15 @@ __global__ __launch_bounds__(256) void k_union_small(const float *__restrict__ s
 // ----------------------------------- border points repeated on the fly, d <= 4
 // Work item = (group of R listed non-core rows, column chunk); a persistent
 // grid strides over the items.  Each item records the first core neighbour
-// in its chunk with atomicMin, so the lowest-index one survives.
+// in its chunk with atomicMin, so the lowest-index one survives.  With a
+// spatial order (okey: caller's index of each staged row) the item takes the
+// smallest okey over all the core neighbours in its chunk instead.
 template <int D, int R>
 __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ soa,
                                                       const uint32_t *__restrict__ corebits,
                                                       const int *__restrict__ list,
                                                       int *__restrict__ jstar,
+                                                      const int *__restrict__ okey,
                                                       DevState *__restrict__ st, SweepScalars sc) {
   if (skip_sweep(sc, st)) return;
   const int lane = lane_id();
@@ -164,8 +167,13 @@ __global__ __launch_bounds__(256) void k_border_small(const float *__restrict__ 
           const uint64_t in =
               settle_band<D>(m, __ballot(s <= sc.lo) & cw, xr[r], xc, sc.eps2, st);
           if (in != 0ull) {
-            found[r] = cb + __builtin_ctzll(in);
-            active &= ~(1u << r);
+            if (okey) {
+              for (uint64_t m2 = in; m2 != 0ull; m2 &= m2 - 1ull)
+                found[r] = min(found[r], okey[cb + __builtin_ctzll(m2)]);
+            } else {
+              found[r] = cb + __builtin_ctzll(in);
+              active &= ~(1u << r);
+            }
           }
         }
       }
@@ -589,10 +597,10 @@ hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   }
   const dim3 grid(4096), block(256);
   switch (sc.d) {
-    case 1: hipLaunchKernelGGL((k_border_small<1, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
-    case 2: hipLaunchKernelGGL((k_border_small<2, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
-    case 3: hipLaunchKernelGGL((k_border_small<3, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
-    case 4: hipLaunchKernelGGL((k_border_small<4, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.st, sc); break;
+    case 1: hipLaunchKernelGGL((k_border_small<1, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.okey, b.st, sc); break;
+    case 2: hipLaunchKernelGGL((k_border_small<2, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.okey, b.st, sc); break;
+    case 3: hipLaunchKernelGGL((k_border_small<3, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.okey, b.st, sc); break;
+    case 4: hipLaunchKernelGGL((k_border_small<4, kRowsSmall>), grid, block, 0, s, b.soa, b.corebits, b.list, b.jstar, b.okey, b.st, sc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

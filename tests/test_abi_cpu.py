@@ -95,6 +95,43 @@ def test_workspace_size_layout():
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(bm), ctypes.byref(out)) == _lib.DBSCAN_E_UNSUPPORTED
 
 
+def test_order_option_layout():
+    """The spatial order (default for the float32 forms at d <= 4) adds seven
+    n_pad-sized int32 arrays (sort keys and values, two of each; inverse
+    permutation; staged-order counts; per-root label minima) and the radix
+    histograms (256 per 2048-key tile); it is refused where it does not apply."""
+    L = _lib.load()
+    out = ctypes.c_uint64()
+    n, n_pad = 200_000, 200_192
+
+    def size(**kw):
+        o = _lib.make_opts(**kw)
+        rc = L.dbscan_workspace_size(n, 2, ctypes.byref(o), ctypes.byref(out))
+        assert rc == 0
+        return out.value
+
+    def r256(b):
+        return (b + 255) // 256 * 256
+
+    hist = 256 * ((n + 2047) // 2048) * 4
+    extra = 7 * r256(n_pad * 4) + r256(hist)
+    for adj in ("bitmask", "onthefly"):
+        assert size(adjacency=adj, order="spatial") - size(adjacency=adj, order="input") == extra
+        assert size(adjacency=adj) == size(adjacency=adj, order="spatial")  # auto
+    o = _lib.make_opts("onthefly", "fp32", order="spatial")
+    assert L.dbscan_workspace_size(1000, 5, ctypes.byref(o), ctypes.byref(out)) == \
+        _lib.DBSCAN_E_UNSUPPORTED
+    o = _lib.make_opts("onthefly", "fp16", order="spatial")
+    assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == \
+        _lib.DBSCAN_E_UNSUPPORTED
+    o = _lib.make_opts(order="input")
+    o.order = 9
+    assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+    o.order = 0
+    o.reserved = 1
+    assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+
+
 def _band(eps2, d):
     L = _lib.load()
     lo, hi = ctypes.c_float(), ctypes.c_float()
