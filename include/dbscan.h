@@ -180,7 +180,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
 /*
  * dbscan_workspace_size -- bytes of device scratch dbscan_fit_ex needs for
  * (n, d, opts); *bytes (HOST) receives the size.  The bitmask adjacency needs
- * ceil(n/256)*256 * ceil(n/256)*256 / 8 bytes; the on-the-fly form needs O(n*d).
+ * n_pad * n_pad / 8 bytes plus a flag byte per 32 x 64 tile (n_pad^2 / 2048),
+ * n_pad = ceil(n/256)*256; the on-the-fly form needs O(n*d).
  */
 int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_t *bytes);
 

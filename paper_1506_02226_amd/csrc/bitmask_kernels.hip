@@ -19,7 +19,13 @@ namespace dbk {
 // row0..row0+31, column j); by symmetry that is row j's word for the columns
 // row0..row0+31, stored at adj[row0/32][j] -- a coalesced 256-byte store per
 // wave.  Bit b of adj[q][i] is the pair (i, 32q+b).  Padded rows and columns
-// (index >= n) are NaN, so their bits are zero.
+// (index >= n) are NaN, so their bits are zero.  Each 32 x 64 tile also gets
+// a flag byte, tflag[j/64][row0/32], telling whether any of its bits is set
+// (the merge reads only flagged tiles); the flags are gathered in LDS and
+// written once per block.  The words themselves are stored unconditionally:
+// a store that only some iterations make leaves the compiler unable to count
+// the memory operations in flight, and the next column block's prefetched
+// coordinates would then wait for the store to complete.
 //
 // The relation is symmetric, so each unordered pair is tested once: a 16-row
 // block only visits the 64-column blocks from the one holding its own rows
@@ -34,14 +40,17 @@ namespace dbk {
 // the sc.chunk columns of one chunk; the grid is row groups x chunks, and a
 // block whose columns all lie before its rows has nothing to do.
 constexpr int kBitmaskMaxChunk = 4096;
+constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 
 template <int D>
 __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
                                                  uint32_t *__restrict__ adj,
+                                                 uint8_t *__restrict__ tflag,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
-  constexpr int R = 32, G = 4;
+  constexpr int R = 32, G = 8;
   __shared__ int colcnt[kBitmaskMaxChunk];
+  __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];  // non-empty flags
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
   const int chunk = blockIdx.x % sc.nchunks;
@@ -66,6 +75,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 #pragma unroll
     for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
     uint32_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
+    uint8_t *flag = tiles[(row0 - g0) / R];  // [column block - c0 / 64]
     float xn[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
@@ -79,26 +89,22 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
       }
       uint32_t word = 0;
       // rows in groups of G: the common case (no neighbour among the 64
-      // columns for any of the G rows) costs one compare per row and one
-      // branch per group; the lane's bits and the row counts are set only
-      // in the rare case
+      // columns for any of the G rows) costs one compare of the group's
+      // minimum and one branch; the rows' ballots, the lane's bits and the
+      // row counts are taken only in the rare case
 #pragma unroll
       for (int g = 0; g < R / G; ++g) {
         float sg[G];
-        uint64_t mg[G], any = 0ull;
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-          sg[k] = sq_dist32<D>(xr[g * G + k], xc);
-          mg[k] = __ballot(sg[k] <= sc.hi);
-          any |= mg[k];
-        }
-        if (any == 0ull) continue;
+        for (int k = 0; k < G; ++k) sg[k] = sq_dist32<D>(xr[g * G + k], xc);
+        if (__ballot(min_of<G>(sg) <= sc.hi) == 0ull) continue;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
           const int r = g * G + k;
-          if (mg[k] == 0ull) continue;
+          const uint64_t mk = __ballot(sg[k] <= sc.hi);
+          if (mk == 0ull) continue;
           const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
-          uint64_t in = mg[k];
+          uint64_t in = mk;
           if (lo_m != in)
             in = recheck_band_soa(in & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
                                   sc.eps2, st);
@@ -107,6 +113,8 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
         }
       }
       out[cb + lane] = word;
+      const bool filled = __ballot(word != 0u) != 0ull;
+      if (lane == 0) flag[(cb - c0) >> 6] = filled ? 1 : 0;
       if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
     }
     int mine = 0;
@@ -121,26 +129,141 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
     const int v = colcnt[t];
     if (v != 0 && c0 + t < sc.n) atomicAdd(counts + c0 + t, v);
   }
+  // flags of the tiles this block computed: 32-row block q, column block
+  // cb >= the diagonal block of q's rows
+  const int nq = sc.n_pad / 32, nr = (g1 - g0) / 32, nc = (c1 - c0) / 64;
+  for (int t = threadIdx.x; t < nr * nc; t += 256) {
+    const int rr = t % nr, cc = t / nr;
+    const int q = g0 / 32 + rr, cb = c0 + 64 * cc;
+    if (cb >= ((32 * q) & ~63)) tflag[(size_t)(cb >> 6) * nq + q] = tiles[rr][cc];
+  }
 }
 
 // --------------------------------------------------- merge from the bitmask
-// Step 3 and the border points in one read of the lower triangle.  One wave
-// owns 64 rows i (lanes) and walks the 32-column words q of a chunk up to the
-// diagonal, so it sees every neighbour pair (i, j), j < i, once, and takes
-// the set bits of its word one per lane per round:
-//  * core i, core j: queued, and the queue is drained into the union-find 64
-//    pairs at a time;
-//  * core i, non-core j: i is a core neighbour of j (atomicMin on jstar[j]);
-//  * non-core i: its first core j in ascending order is its lowest core
-//    neighbour below it (atomicMin on jstar[i], then the row stops looking).
+// Step 3 and the border points, from the lower triangle of the bitmask, in
+// three passes.  All read only the 32 x 64 tiles flagged non-empty (64 flags
+// at a time), and one wave owns 64 rows i (lanes).
+//
+//  1. k_merge_hook: every core row i hooks under its lowest-index core
+//     neighbour j < i among the 2048 columns below its 64-row block (the
+//     first core bit in ascending column order).  Only row i writes
+//     parent[i], and j < i, so this is a plain store and the forest keeps
+//     parent[v] <= v.  It only speeds up pass 3 (which sees every pair), and
+//     with rows in spatial order most of each cluster is joined here.
+//  2. k_merge_compress: parent[v] = root of v.
+//  3. k_merge_bitmask: every neighbour pair (i, j), j < i, once:
+//     * core i, core j: joined in the union-find unless j's parent already
+//       equals i's root.  A word's 32 column parents are loaded once (one
+//       per lane) and compared through cross-lane reads; when all its core
+//       columns share one parent, one union stands for the whole word.
+//       Unions are queued and drained 64 at a time;
+//     * core i, non-core j: i is a core neighbour of j (atomicMin on
+//       jstar[j]);
+//     * non-core i: its first core j in ascending order is its lowest core
+//       neighbour below it (atomicMin on jstar[i], then the row stops
+//       looking).
 // A non-core point's core neighbours above it are found by those rows, so
 // after the pass jstar[v] is the lowest-index core neighbour of every
 // non-core v.  With a spatial order (ORDERED) the index that counts is the
 // caller's, okey[j]: jstar takes okey values, and a non-core row takes the
 // smallest okey over all its core neighbours below it instead of stopping
 // at the first.
+//
+// Skipping a pair is safe whatever the timing: parent values only ever move
+// to ancestors, so equal values mean a common ancestor, i.e. one tree.
+
+// Rows of the wave that owns 64-row block rb, the words of the chunk and
+// their flags: the common prologue of the passes.
+struct MergeRows {
+  int i, qi, q0, q1;
+  bool valid, is_core;
+  const uint8_t *flags;
+};
+
+__device__ __forceinline__ MergeRows merge_rows(const uint8_t *__restrict__ tflag,
+                                                const uint32_t *__restrict__ corebits, int rb,
+                                                int chunk, const SweepScalars &p) {
+  MergeRows m;
+  m.i = rb * 64 + lane_id();
+  m.valid = m.i < p.n;
+  m.is_core = m.valid && ((corebits[m.i >> 5] >> (m.i & 31)) & 1u);
+  m.qi = m.i >> 5;
+  m.q0 = chunk * p.chunk;
+  m.q1 = min(m.q0 + p.chunk, (rb * 64 + 63) / 32 + 1);  // lower triangle
+  m.flags = tflag + (size_t)rb * (p.n_pad / 32);
+  return m;
+}
+
+// The word of row m.i for columns 32q..32q+31, limited to columns j < i.
+__device__ __forceinline__ uint32_t lower_word(const MergeRows &m, int q, uint32_t word) {
+  if (!m.valid || q > m.qi || q >= m.q1) return 0u;
+  if (q == m.qi) return word & ((1u << (m.i & 31)) - 1u);
+  return word;
+}
+
+constexpr int kMergeLoads = 8;  // words in flight per lane
+
+// Calls f(q, word) for the flagged words q of the chunk, ascending, kU at a
+// time loaded before any is used (the loop is bound by load latency
+// otherwise), while `more` (a wave-uniform predicate) holds.
+template <typename F, typename M>
+__device__ __forceinline__ void for_flagged_words(const uint32_t *__restrict__ adj,
+                                                  const MergeRows &m, int n_pad, F &&f,
+                                                  M &&more) {
+  const int lane = lane_id();
+  for (int qf = m.q0; qf < m.q1 && more(); qf += 64) {
+    uint64_t pend = __ballot(qf + lane < m.q1 && m.flags[qf + lane] != 0);
+    while (pend != 0ull && more()) {
+      int qs[kMergeLoads];
+      uint32_t wv[kMergeLoads];
+#pragma unroll
+      for (int u = 0; u < kMergeLoads; ++u) {
+        qs[u] = m.q1;  // none
+        if (pend != 0ull) {
+          qs[u] = qf + __builtin_ctzll(pend);
+          pend &= pend - 1ull;
+        }
+        wv[u] = (qs[u] < m.q1) ? adj[(size_t)qs[u] * n_pad + m.i] : 0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kMergeLoads; ++u) f(qs[u], lower_word(m, qs[u], wv[u]));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_merge_hook(const uint32_t *__restrict__ adj,
+                                                    const uint8_t *__restrict__ tflag,
+                                                    const uint32_t *__restrict__ corebits,
+                                                    int *__restrict__ parent, SweepScalars p) {
+  const int rb = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (rb * 64 >= p.n) return;
+  MergeRows m = merge_rows(tflag, corebits, rb, 0, p);
+  m.q0 = max(0, m.q1 - 64);  // one batch of flags: the window below the diagonal
+  bool seek = m.is_core;
+  for_flagged_words(
+      adj, m, p.n_pad,
+      [&](int q, uint32_t word) {
+        if (!seek || word == 0u) return;
+        const uint32_t hit = word & corebits[q < m.q1 ? q : 0];
+        if (hit != 0u) {
+          parent[m.i] = q * 32 + __builtin_ctz(hit);
+          seek = false;
+        }
+      },
+      [&]() { return __ballot(seek) != 0ull; });
+}
+
+__global__ void k_merge_compress(int *__restrict__ parent, int n) {
+  const int i = blockIdx.x * 256 + (int)threadIdx.x;
+  if (i < n) {
+    const int r = uf_find(parent, i);
+    if (r != i) uf_store(parent + i, r);
+  }
+}
+
 template <bool ORDERED>
 __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restrict__ adj,
+                                                       const uint8_t *__restrict__ tflag,
                                                        const uint32_t *__restrict__ corebits,
                                                        int *__restrict__ parent,
                                                        int *__restrict__ jstar,
@@ -152,74 +275,78 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   const int chunk = blockIdx.x % p.nchunks;
   const int rb = (blockIdx.x / p.nchunks) * 4 + w;
   if (rb * 64 >= p.n) return;
-  const int i = rb * 64 + lane;
-  const bool valid = i < p.n;
-  const bool is_core = valid && ((corebits[i >> 5] >> (i & 31)) & 1u);
-  bool seek = valid && !is_core;
-  int best = kNoNeighbour;                               // ORDERED, non-core rows
-  const int my_key = (ORDERED && valid) ? okey[i] : i;  // key of row i in jstar
-  const int qi = i >> 5;
-  const int q0 = chunk * p.chunk;
-  const int q1 = min(q0 + p.chunk, (rb * 64 + 63) / 32 + 1);  // lower triangle
-  if (q0 >= q1) return;
+  const MergeRows m = merge_rows(tflag, corebits, rb, chunk, p);
+  if (m.q0 >= m.q1) return;
+  const int i = m.i;
+  bool seek = m.valid && !m.is_core;
+  int best = kNoNeighbour;                                 // ORDERED, non-core rows
+  const int my_key = (ORDERED && m.valid) ? okey[i] : i;  // key of row i in jstar
+  const int root_i = m.is_core ? parent[i] : -1;          // after the compress pass
   WaveQueue qu{qbuf[w], 0, 64};
-  // kU words per lane are loaded before any is used, so that kU loads per
-  // wave are in flight (the loop is bound by load latency otherwise)
-  constexpr int kU = 8;
-  for (int qb = q0; qb < q1; qb += kU) {
-    uint32_t wv[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int q = qb + u;
-      wv[u] = (q < q1) ? adj[(size_t)q * p.n_pad + i] : 0u;
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int q = qb + u;
-      uint32_t word = wv[u];
-      if (!valid || q > qi || q >= q1) word = 0u;
-      else if (q == qi) word &= (1u << (i & 31)) - 1u;
-      if (__ballot(word != 0u) == 0ull) continue;
-      const uint32_t cw = corebits[q];  // core flags of the columns 32q..32q+31
-      if (!is_core) {
-        uint32_t hit = word & cw;
-        if (ORDERED) {
-          // the smallest caller index among the core neighbours
-          for (; hit != 0u; hit &= hit - 1u) best = min(best, okey[q * 32 + __builtin_ctz(hit)]);
-        } else if (seek && hit != 0u) {
-          // the first core neighbour of a non-core row, in ascending order
-          atomicMin(jstar + i, q * 32 + __builtin_ctz(hit));
-          seek = false;
+  for_flagged_words(
+      adj, m, p.n_pad,
+      [&](int q, uint32_t word) {
+        // every lane takes part in the cross-lane steps: no per-lane return
+        if (__ballot(word != 0u) == 0ull) return;
+        const uint32_t cw = corebits[q];  // core flags of the columns 32q..32q+31
+        if (!m.is_core) {
+          uint32_t hit = word & cw;
+          if (ORDERED) {
+            // the smallest caller index among the core neighbours
+            for (; hit != 0u; hit &= hit - 1u)
+              best = min(best, okey[q * 32 + __builtin_ctz(hit)]);
+          } else if (seek && hit != 0u) {
+            // the first core neighbour of a non-core row, in ascending order
+            atomicMin(jstar + i, q * 32 + __builtin_ctz(hit));
+            seek = false;
+          }
+        } else {
+          // core row: its non-core columns take i as a core neighbour
+          for (uint32_t nc = word & ~cw; nc != 0u; nc &= nc - 1u)
+            atomicMin(jstar + q * 32 + __builtin_ctz(nc), my_key);
         }
-        word = 0u;
-      }
-      while (__ballot(word != 0u) != 0ull) {
-        const bool has = word != 0u;
-        const int b = has ? __builtin_ctz(word) : 0;
-        word &= word - 1u;
-        const int j = q * 32 + b;
-        const bool cj = (cw >> b) & 1u;
-        if (has && is_core && !cj) atomicMin(jstar + j, my_key);
-        wq_push(qu, has && is_core && cj, i, j);
-        wq_drain_union(qu, parent, false);
-      }
-    }
-  }
+        // core-core pairs: unions only where the parents differ
+        uint32_t cc = m.is_core ? (word & cw) : 0u;
+        if (__ballot(cc != 0u) == 0ull) return;
+        const int pc = parent[q * 32 + (lane & 31)];  // lanes l and l + 32: column l
+        const int P = __builtin_amdgcn_readlane(pc, __builtin_ctz(cw));
+        if (__ballot(((cw >> (lane & 31)) & 1u) && pc != P) == 0ull) {
+          // every core column hangs under P: at most one union for the word
+          wq_push(qu, cc != 0u && root_i != P, i, q * 32 + (cc ? __builtin_ctz(cc) : 0));
+          wq_drain_union(qu, parent, false);
+          return;
+        }
+        uint32_t need = 0u;
+        for (uint32_t c2 = cw; c2 != 0u; c2 &= c2 - 1u) {
+          const int b = __builtin_ctz(c2);
+          need |= (__builtin_amdgcn_readlane(pc, b) != root_i) ? (1u << b) : 0u;
+        }
+        cc &= need;
+        while (__ballot(cc != 0u) != 0ull) {
+          const bool has = cc != 0u;
+          const int b = has ? __builtin_ctz(cc) : 0;
+          cc &= cc - 1u;
+          wq_push(qu, has, i, q * 32 + b);
+          wq_drain_union(qu, parent, false);
+        }
+      },
+      []() { return true; });
   if (ORDERED && best != kNoNeighbour) atomicMin(jstar + i, best);
   wq_drain_union(qu, parent, true);
 }
 
 // ------------------------------------------------------------ host launchers
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
-  if (sc.chunk % 64 != 0 || sc.chunk > kBitmaskMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0)
+  if (sc.chunk % 64 != 0 || sc.chunk > kBitmaskMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0 ||
+      sc.rgroup > kBitmaskMaxRows)
     return hipErrorInvalidValue;
   const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
   const dim3 grid(groups * sc.nchunks), block(256);
   switch (sc.d) {
-    case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
-    case 2: hipLaunchKernelGGL(k_bitmask<2>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
-    case 3: hipLaunchKernelGGL(k_bitmask<3>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
-    case 4: hipLaunchKernelGGL(k_bitmask<4>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.counts, b.st, sc); break;
+    case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
+    case 2: hipLaunchKernelGGL(k_bitmask<2>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
+    case 3: hipLaunchKernelGGL(k_bitmask<3>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
+    case 4: hipLaunchKernelGGL(k_bitmask<4>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -227,12 +354,20 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
+  SweepScalars whole = sc;  // the hook pass scans each row's words in one piece
+  whole.nchunks = 1;
+  whole.chunk = sc.n_pad / 32;
+  hipLaunchKernelGGL(k_merge_hook, dim3(groups), dim3(256), 0, s, (const uint32_t *)b.adjT,
+                     b.tflag, b.corebits, b.parent, whole);
+  hipLaunchKernelGGL(k_merge_compress, dim3((sc.n + 255) / 256), dim3(256), 0, s, b.parent, sc.n);
   if (b.okey)
     hipLaunchKernelGGL(k_merge_bitmask<true>, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                       (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, b.okey, sc);
+                       (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
+                       sc);
   else
     hipLaunchKernelGGL(k_merge_bitmask<false>, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                       (const uint32_t *)b.adjT, b.corebits, b.parent, b.jstar, b.okey, sc);
+                       (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
+                       sc);
   return hipGetLastError();
 }
 

@@ -59,14 +59,17 @@ __device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n,
 
 // ------------------------------------------------------------- core flags
 // corebits in the staged order; core[] (and, with a spatial order, the
-// counts) written in the caller's order.
+// counts) written in the caller's order.  With `count` the number of core
+// points goes to st->core_points (one atomic per block).  Every thread of the
+// block must call it (it synchronises the block).
 __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n, int n_pad,
                                           int minpts, uint8_t *__restrict__ core,
                                           uint32_t *__restrict__ corebits, DevState *st, int bid,
                                           const int *__restrict__ perm = nullptr,
-                                          int *__restrict__ counts_out = nullptr) {
+                                          int *__restrict__ counts_out = nullptr,
+                                          bool count = false) {
+  __shared__ unsigned block_cores;
   const int i = bid * 256 + (int)threadIdx.x;
-  if (i >= n_pad) return;  // n_pad is a multiple of 64: whole waves
   const bool c = i < n && counts[i] >= minpts;
   if (i < n) {
     if (perm) {
@@ -79,11 +82,16 @@ __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n,
   }
   const uint64_t m = __ballot(c);
   const int lane = lane_id();
-  if (lane == 0) {
+  if (lane == 0 && i < n_pad) {  // n_pad is a multiple of 64: whole waves
     corebits[i >> 5] = (uint32_t)m;
     corebits[(i >> 5) + 1] = (uint32_t)(m >> 32);
-    if (m) atomicAdd(&st->core_points, (unsigned long long)__popcll(m));
   }
+  if (!count) return;  // uniform over the launch
+  if (threadIdx.x == 0) block_cores = 0u;
+  __syncthreads();
+  if (lane == 0 && m) atomicAdd(&block_cores, (unsigned)__popcll(m));
+  __syncthreads();
+  if (threadIdx.x == 0 && block_cores) atomicAdd(&st->core_points, (unsigned long long)block_cores);
 }
 
 // --------------------------------------------- merge + border from the list
@@ -123,8 +131,22 @@ __device__ __forceinline__ void rootmin_body(int n, const uint32_t *__restrict__
                                              const int *__restrict__ perm,
                                              int *__restrict__ rootmin, int bid) {
   const int i = bid * 256 + (int)threadIdx.x;
-  if (i >= n || !((corebits[i >> 5] >> (i & 31)) & 1u)) return;
-  atomicMin(rootmin + uf_find(parent, i), perm[i]);
+  const bool is_core = i < n && ((corebits[i >> 5] >> (i & 31)) & 1u);
+  const int root = is_core ? uf_find(parent, i) : 0;
+  const int key = is_core ? perm[i] : kNoNeighbour;
+  // the lanes of a wave mostly share a root: one atomic per distinct root
+  bool pending = is_core;
+  uint64_t left = __ballot(pending);
+  while (left != 0ull) {
+    const int leader = __builtin_ctzll(left);
+    const int r = __shfl(root, leader);
+    const bool mine = pending && root == r;
+    int v = mine ? key : kNoNeighbour;
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    if (lane_id() == leader) atomicMin(rootmin + r, v);
+    pending = pending && !mine;
+    left = __ballot(pending);
+  }
 }
 
 __device__ __forceinline__ void labels_body(int n, const uint32_t *__restrict__ corebits,

@@ -70,23 +70,19 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       }
       const bool off = cb != diag;
       uint32_t tally = 0;
-      // rows in groups of GR: one branch per group in the common case
+      // rows in groups of GR: one compare of their minimum and one branch
+      // per group in the common case; the rows' own ballots only in the rare
       constexpr int GR = R;
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) {
         float sg[GR];
-        uint64_t mg[GR], any = 0ull;
 #pragma unroll
-        for (int k = 0; k < GR; ++k) {
-          sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
-          mg[k] = __ballot(sg[k] <= sc.hi);
-          any |= mg[k];
-        }
-        if (any == 0ull) continue;
+        for (int k = 0; k < GR; ++k) sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
+        if (__ballot(min_of<GR>(sg) <= sc.hi) == 0ull) continue;
 #pragma unroll
         for (int k = 0; k < GR; ++k) {
           const int r = g * GR + k;
-          const uint64_t m = mg[k];
+          const uint64_t m = __ballot(sg[k] <= sc.hi);
           if (m == 0ull) continue;
           const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
           uint64_t in = m;

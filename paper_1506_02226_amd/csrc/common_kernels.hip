@@ -39,8 +39,10 @@ __global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, 
 // ------------------------------------------------------------- core flags
 __global__ void k_core(const int *__restrict__ counts, int n, int n_pad, int minpts,
                        uint8_t *__restrict__ core, uint32_t *__restrict__ corebits,
-                       DevState *st, const int *__restrict__ perm, int *__restrict__ counts_out) {
-  core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x, perm, counts_out);
+                       DevState *st, const int *__restrict__ perm, int *__restrict__ counts_out,
+                       int count) {
+  core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x, perm, counts_out,
+            count != 0);
 }
 
 // Non-core rows into a list (any order) for the border pass that repeats the
@@ -127,9 +129,9 @@ hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float
 
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
                     uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
-                    hipStream_t s) {
+                    bool count, hipStream_t s) {
   hipLaunchKernelGGL(k_core, dim3((n_pad + 255) / 256), dim3(256), 0, s, counts, n, n_pad, minpts,
-                     core, corebits, st, ord.perm, counts_out);
+                     core, corebits, st, ord.perm, counts_out, count ? 1 : 0);
   return hipGetLastError();
 }
 

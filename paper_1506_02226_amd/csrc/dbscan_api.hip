@@ -32,7 +32,7 @@ struct Layout {
   int precision = DBSCAN_PREC_FP32;
   int order = DBSCAN_ORDER_INPUT;
   uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
-           off_list = 0, off_adj = 0, off_pairs = 0, off_aaug = 0, off_baug = 0, off_band = 0,
+           off_list = 0, off_adj = 0, off_tflag = 0, off_pairs = 0, off_aaug = 0, off_baug = 0, off_band = 0,
            total = 0;
   // spatial order: sort keys and values (two buffers each), digit histograms,
   // the inverse permutation, staged-order counts and per-root label minima
@@ -44,6 +44,8 @@ struct Layout {
 };
 
 uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
+// one byte per 32 x 64 tile of the bitmask: non-empty or not
+uint64_t tile_flag_bytes(int64_t n_pad) { return (uint64_t)n_pad / 64 * (uint64_t)(n_pad / 32); }
 
 int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->n_pad = round_up(n, kPadRows);
@@ -101,6 +103,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->off_corebits = take((uint64_t)L->n_pad / 8);
   L->off_list = take((uint64_t)L->n_pad * 4);
   L->off_adj = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(bitmask_bytes(L->n_pad)) : off;
+  L->off_tflag = (L->adjacency == DBSCAN_ADJ_BITMASK) ? take(tile_flag_bytes(L->n_pad)) : off;
   if (L->adjacency == DBSCAN_ADJ_ONTHEFLY) {
     const uint64_t req = (o && o->pair_capacity) ? o->pair_capacity : (uint64_t)kPairsPerPoint * n;
     L->edge_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);
@@ -382,6 +385,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   bufs.jstar = jstar;
   bufs.list = list;
   bufs.adjT = adjT;
+  bufs.tflag = (uint8_t *)(ws + L.off_tflag);
   bufs.pairs = pairs;
   bufs.band = band;
   bufs.st = st;
@@ -436,7 +440,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   }
   mark(1);
   // ---- step 2: core flags
-  step(dbk::run_core(counts_k, ni, npad, minpts, core, corebits, st, ord, counts, s));
+  // the core-point total is a statistic: counted only when asked for
+  step(dbk::run_core(counts_k, ni, npad, minpts, core, corebits, st, ord, counts,
+                     stats != nullptr, s));
   mark(2);
   // ---- step 3: merge (union-find over core-core neighbour pairs) and border
   // points (lowest-index core neighbour)

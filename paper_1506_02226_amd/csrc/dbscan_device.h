@@ -127,6 +127,24 @@ __device__ __forceinline__ float sq_dist32(const float (&a)[D], const float (&b)
   return s;
 }
 
+// Smallest of G values (G = 4 or 8) as a tree of three-operand minima
+// (v_min3_f32): one compare of the minimum then tells whether any of G
+// squared distances reaches the band, where G compares would cost G
+// instructions at the compare issue rate.  A NaN operand (padded column) is
+// skipped as fminf skips it, and compares false like the value itself.
+template <int G>
+__device__ __forceinline__ float min_of(const float (&v)[G]) {
+  static_assert(G == 4 || G == 8, "group size");
+  if constexpr (G == 4) {
+    return __builtin_fminf(__builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]), v[3]);
+  } else {
+    const float a = __builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]);
+    const float b = __builtin_fminf(__builtin_fminf(v[3], v[4]), v[5]);
+    const float c = __builtin_fminf(__builtin_fminf(v[6], v[7]), a);
+    return __builtin_fminf(b, c);
+  }
+}
+
 // Re-decide the lanes in `band` in float64; returns the exact in-mask.
 template <int D>
 __device__ __forceinline__ uint64_t recheck_band(uint64_t band, uint64_t in, const float (&a)[D],

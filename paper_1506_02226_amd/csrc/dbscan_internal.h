@@ -18,6 +18,7 @@ struct Buffers {
   int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
   const int *list;     // [n_pad] compacted non-core rows
   void *adjT;          // [n_pad/32][n_pad] uint32 bitmask adjacency (bitmask form only)
+  uint8_t *tflag;      // [n_pad/64][n_pad/32] non-empty flags of its 32 x 64 tiles
   int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
   int2 *band;          // [band_cap] pairs the matrix-core filter leaves undecided
   DevState *st;
@@ -81,7 +82,7 @@ hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
                     uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
-                    hipStream_t s);
+                    bool count, hipStream_t s);
 hipError_t run_compact_noncore(const uint32_t *corebits, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);

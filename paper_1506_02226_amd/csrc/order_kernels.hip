@@ -30,10 +30,15 @@ __device__ __forceinline__ float from_ordered(unsigned o) {
   return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
 }
 
-// Bounding box of the finite coordinates: wave reductions, then one atomic
-// per wave and coordinate into st->box_lo / box_hi (reset to empty).
+// Bounding box of the finite coordinates: per-thread extremes over a
+// grid-strided range, reduced across the wave and then the block, and one
+// atomic per block and coordinate into st->box_lo / box_hi (reset to empty).
+// The grid is small (at most kBoxBlocks), so the atomics do not queue up.
+constexpr int kBoxBlocks = 256;
+
 __global__ __launch_bounds__(256) void k_order_box(const float *__restrict__ pts, int n, int d,
                                                    DevState *st) {
+  __shared__ unsigned red[2][4][4];  // [lo / hi][wave][coordinate]
   unsigned lo[4] = {~0u, ~0u, ~0u, ~0u}, hi[4] = {0u, 0u, 0u, 0u};
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
        i += (long long)gridDim.x * 256) {
@@ -45,16 +50,25 @@ __global__ __launch_bounds__(256) void k_order_box(const float *__restrict__ pts
       hi[k] = max(hi[k], o);
     }
   }
-  for (int k = 0; k < d; ++k) {
+  const int w = threadIdx.x >> 6;
+  for (int k = 0; k < 4; ++k) {
     unsigned a = lo[k], b = hi[k];
     for (int off = 32; off > 0; off >>= 1) {
       a = min(a, (unsigned)__shfl_xor((int)a, off));
       b = max(b, (unsigned)__shfl_xor((int)b, off));
     }
     if (lane_id() == 0) {
-      if (a != ~0u) atomicMin(&st->box_lo[k], a);
-      if (b != 0u) atomicMax(&st->box_hi[k], b);
+      red[0][w][k] = a;
+      red[1][w][k] = b;
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < d) {
+    const int k = threadIdx.x;
+    const unsigned a = min(min(red[0][0][k], red[0][1][k]), min(red[0][2][k], red[0][3][k]));
+    const unsigned b = max(max(red[1][0][k], red[1][1][k]), max(red[1][2][k], red[1][3][k]));
+    if (a != ~0u) atomicMin(&st->box_lo[k], a);
+    if (b != 0u) atomicMax(&st->box_hi[k], b);
   }
 }
 
@@ -81,7 +95,7 @@ __global__ __launch_bounds__(256) void k_order_keys(const float *__restrict__ pt
   vals[i] = (int)i;
 }
 
-// Digit histogram of each tile: hist[digit * ntiles + tile].
+// Digit histogram of each tile: hist[tile * 256 + digit].
 __global__ __launch_bounds__(256) void k_sort_hist(const unsigned *__restrict__ keys, int n,
                                                    int shift, int *__restrict__ hist, int ntiles) {
   __shared__ int h[256];
@@ -94,32 +108,38 @@ __global__ __launch_bounds__(256) void k_sort_hist(const unsigned *__restrict__ 
     if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1);
   }
   __syncthreads();
-  hist[(long long)tid * ntiles + blockIdx.x] = h[tid];
+  hist[(long long)blockIdx.x * 256 + tid] = h[tid];
 }
 
-// Exclusive prefix sum of hist[0..m) in place (one block): each thread sums
-// a contiguous segment, the segment sums are scanned in LDS, then each
-// thread rewrites its segment.
-__global__ __launch_bounds__(1024) void k_sort_scan(int *__restrict__ hist, long long m) {
-  __shared__ int part[1024];
-  const int tid = threadIdx.x;
-  const long long per = (m + 1023) / 1024;
-  const long long b = tid * per;
-  const long long e = min(b + per, m);
-  int s = 0;
-  for (long long j = b; j < e; ++j) s += hist[j];
-  part[tid] = s;
+// Turns the tile histograms into each tile's first output index per digit:
+// hist[t][g] = (keys with a digit below g) + (keys with digit g in tiles
+// before t).  One block; thread (segment s, digit g) owns digit g over a
+// quarter of the tiles, so every load of the block is 1 KiB contiguous.
+__global__ __launch_bounds__(1024) void k_sort_scan(int *__restrict__ hist, int ntiles) {
+  __shared__ int seg[4][256];
+  __shared__ int base[256];
+  const int g = threadIdx.x & 255, sgm = threadIdx.x >> 8;
+  const int per = (ntiles + 3) / 4;
+  const int t0 = sgm * per, t1 = min(t0 + per, ntiles);
+  int sum = 0;
+  for (int t = t0; t < t1; ++t) sum += hist[(long long)t * 256 + g];
+  seg[sgm][g] = sum;
   __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = tid >= off ? part[tid - off] : 0;
+  if (sgm == 0) base[g] = seg[0][g] + seg[1][g] + seg[2][g] + seg[3][g];
+  __syncthreads();
+  // exclusive scan of the 256 digit totals (threads of segment 0)
+  for (int off = 1; off < 256; off <<= 1) {
+    const int v = (sgm == 0 && g >= off) ? base[g - off] : 0;
     __syncthreads();
-    part[tid] += v;
+    if (sgm == 0) base[g] += v;
     __syncthreads();
   }
-  int run = tid ? part[tid - 1] : 0;
-  for (long long j = b; j < e; ++j) {
-    const int v = hist[j];
-    hist[j] = run;
+  int run = (g ? base[g - 1] : 0);
+  for (int k = 0; k < sgm; ++k) run += seg[k][g];
+  for (int t = t0; t < t1; ++t) {
+    const long long e = (long long)t * 256 + g;
+    const int v = hist[e];
+    hist[e] = run;
     run += v;
   }
 }
@@ -138,7 +158,7 @@ __global__ __launch_bounds__(256) void k_sort_scatter(const unsigned *__restrict
   __shared__ int wcnt[4][256];
   const int tid = threadIdx.x;
   const int w = tid >> 6;
-  run[tid] = hist[(long long)tid * ntiles + blockIdx.x];
+  run[tid] = hist[(long long)blockIdx.x * 256 + tid];
 #pragma unroll
   for (int k = 0; k < 4; ++k) wcnt[k][tid] = 0;
   __syncthreads();
@@ -181,8 +201,8 @@ hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], 
                              int *hist, DevState *st, int **perm, hipStream_t s) {
   if (d < 1 || d > 4 || n < 1) return hipErrorInvalidValue;
   const int blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_order_box, dim3(blocks < 1024 ? blocks : 1024), dim3(256), 0, s, pts, n, d,
-                     st);
+  hipLaunchKernelGGL(k_order_box, dim3(blocks < kBoxBlocks ? blocks : kBoxBlocks), dim3(256), 0, s,
+                     pts, n, d, st);
   hipLaunchKernelGGL(k_order_keys, dim3(blocks), dim3(256), 0, s, pts, n, d, st, keys[0], vals[0]);
   const int ntiles = (n + kSortTile - 1) / kSortTile;
   const int passes = (order_bits_per_coord(d) * d + 7) / 8;
@@ -191,7 +211,7 @@ hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], 
     const int shift = 8 * p;
     hipLaunchKernelGGL(k_sort_hist, dim3(ntiles), dim3(256), 0, s, keys[cur], n, shift, hist,
                        ntiles);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, 256LL * ntiles);
+    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, ntiles);
     hipLaunchKernelGGL(k_sort_scatter, dim3(ntiles), dim3(256), 0, s, keys[cur], vals[cur],
                        keys[cur ^ 1], vals[cur ^ 1], n, shift, hist, ntiles);
     cur ^= 1;
