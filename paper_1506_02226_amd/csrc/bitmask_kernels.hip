@@ -140,23 +140,28 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
 }
 
 // --------------------------------------------------- merge from the bitmask
-// Step 3 and the border points, from the lower triangle of the bitmask, in
-// three passes.  All read only the 32 x 64 tiles flagged non-empty (64 flags
-// at a time), and one wave owns 64 rows i (lanes).
+// Step 3 and the border points, from the lower triangle of the bitmask.  The
+// passes read only the 32 x 64 tiles flagged non-empty (64 flags at a time),
+// and one wave owns 64 rows i (lanes).  With rows in spatial order, first:
 //
 //  1. k_merge_hook: every core row i hooks under its lowest-index core
 //     neighbour j < i among the 2048 columns below its 64-row block (the
 //     first core bit in ascending column order).  Only row i writes
 //     parent[i], and j < i, so this is a plain store and the forest keeps
-//     parent[v] <= v.  It only speeds up pass 3 (which sees every pair), and
-//     with rows in spatial order most of each cluster is joined here.
+//     parent[v] <= v.  It only speeds up the last pass (which sees every
+//     pair): most of each cluster is joined here.
 //  2. k_merge_compress: parent[v] = root of v.
+//
+// Then, in either order:
+//
 //  3. k_merge_bitmask: every neighbour pair (i, j), j < i, once:
-//     * core i, core j: joined in the union-find unless j's parent already
-//       equals i's root.  A word's 32 column parents are loaded once (one
-//       per lane) and compared through cross-lane reads; when all its core
-//       columns share one parent, one union stands for the whole word.
-//       Unions are queued and drained 64 at a time;
+//     * core i, core j: joined in the union-find (queued, drained 64 pairs
+//       at a time).  In spatial order the word's 32 column parents are
+//       loaded too (one per lane): when all its core columns hang under one
+//       parent P -- the common case there -- the word needs no union if P is
+//       i's root and one union otherwise.  (In the caller's order the
+//       parents of a word's columns rarely agree and the loads would only
+//       add latency.)
 //     * core i, non-core j: i is a core neighbour of j (atomicMin on
 //       jstar[j]);
 //     * non-core i: its first core j in ascending order is its lowest core
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   bool seek = m.valid && !m.is_core;
   int best = kNoNeighbour;                                 // ORDERED, non-core rows
   const int my_key = (ORDERED && m.valid) ? okey[i] : i;  // key of row i in jstar
-  const int root_i = m.is_core ? parent[i] : -1;          // after the compress pass
+  const int root_i = (ORDERED && m.is_core) ? parent[i] : -1;  // after the compress pass
   WaveQueue qu{qbuf[w], 0, 64};
   for_flagged_words(
       adj, m, p.n_pad,
@@ -305,23 +310,19 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
           for (uint32_t nc = word & ~cw; nc != 0u; nc &= nc - 1u)
             atomicMin(jstar + q * 32 + __builtin_ctz(nc), my_key);
         }
-        // core-core pairs: unions only where the parents differ
+        // core-core pairs
         uint32_t cc = m.is_core ? (word & cw) : 0u;
         if (__ballot(cc != 0u) == 0ull) return;
-        const int pc = parent[q * 32 + (lane & 31)];  // lanes l and l + 32: column l
-        const int P = __builtin_amdgcn_readlane(pc, __builtin_ctz(cw));
-        if (__ballot(((cw >> (lane & 31)) & 1u) && pc != P) == 0ull) {
-          // every core column hangs under P: at most one union for the word
-          wq_push(qu, cc != 0u && root_i != P, i, q * 32 + (cc ? __builtin_ctz(cc) : 0));
-          wq_drain_union(qu, parent, false);
-          return;
+        if (ORDERED) {
+          const int pc = parent[q * 32 + (lane & 31)];  // lanes l and l + 32: column l
+          const int P = __builtin_amdgcn_readlane(pc, __builtin_ctz(cw));
+          if (__ballot(((cw >> (lane & 31)) & 1u) && pc != P) == 0ull) {
+            // every core column hangs under P: at most one union for the word
+            wq_push(qu, cc != 0u && root_i != P, i, q * 32 + (cc ? __builtin_ctz(cc) : 0));
+            wq_drain_union(qu, parent, false);
+            return;
+          }
         }
-        uint32_t need = 0u;
-        for (uint32_t c2 = cw; c2 != 0u; c2 &= c2 - 1u) {
-          const int b = __builtin_ctz(c2);
-          need |= (__builtin_amdgcn_readlane(pc, b) != root_i) ? (1u << b) : 0u;
-        }
-        cc &= need;
         while (__ballot(cc != 0u) != 0ull) {
           const bool has = cc != 0u;
           const int b = has ? __builtin_ctz(cc) : 0;
@@ -354,12 +355,15 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
-  SweepScalars whole = sc;  // the hook pass scans each row's words in one piece
-  whole.nchunks = 1;
-  whole.chunk = sc.n_pad / 32;
-  hipLaunchKernelGGL(k_merge_hook, dim3(groups), dim3(256), 0, s, (const uint32_t *)b.adjT,
-                     b.tflag, b.corebits, b.parent, whole);
-  hipLaunchKernelGGL(k_merge_compress, dim3((sc.n + 255) / 256), dim3(256), 0, s, b.parent, sc.n);
+  if (b.okey) {
+    SweepScalars whole = sc;  // the hook pass scans each row's words in one piece
+    whole.nchunks = 1;
+    whole.chunk = sc.n_pad / 32;
+    hipLaunchKernelGGL(k_merge_hook, dim3(groups), dim3(256), 0, s, (const uint32_t *)b.adjT,
+                       b.tflag, b.corebits, b.parent, whole);
+    hipLaunchKernelGGL(k_merge_compress, dim3((sc.n + 255) / 256), dim3(256), 0, s, b.parent,
+                       sc.n);
+  }
   if (b.okey)
     hipLaunchKernelGGL(k_merge_bitmask<true>, dim3(groups * sc.nchunks), dim3(256), 0, s,
                        (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
