@@ -72,7 +72,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       uint32_t tally = 0;
       // rows in groups of GR: one compare of their minimum and one branch
       // per group in the common case; the rows' own ballots only in the rare
-      constexpr int GR = R;
+      constexpr int GR = R > 8 ? 8 : R;
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) {
         float sg[GR];

@@ -495,7 +495,7 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
 }
 
 // ------------------------------------------------------------ host launchers
-constexpr int kRowsSmall = 8;  // rows per wave, d <= 4 (scalar registers)
+constexpr int kRowsSmall = 16;  // rows per wave, d <= 4 (vector registers)
 constexpr int kRowsLds = 8;    // rows per wave, d > 4 (LDS)
 
 int rows_per_wave(int d) { return d <= 4 ? kRowsSmall : kRowsLds; }
