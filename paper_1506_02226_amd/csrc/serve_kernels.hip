@@ -19,7 +19,7 @@
 
 namespace dbk {
 
-constexpr int kServeRows = 8;      // rows per wave of the float32 sweep
+constexpr int kServeRows = 16;     // rows per wave of the float32 sweep
 constexpr int kIdlePolls = 256;    // idle polls (~0.2 us each) before a block leaves
 
 union ServeLds {
