@@ -70,7 +70,8 @@ extern "C" {
 
 /* Order in which the rows are processed (results are always returned in the
  * caller's order and are identical either way). */
-#define DBSCAN_ORDER_AUTO 0    /* spatial for the float32 forms with d <= 4, else input */
+#define DBSCAN_ORDER_AUTO 0    /* spatial for the float32 forms with d <= 4 and
+                                  n >= 65536, else input */
 #define DBSCAN_ORDER_INPUT 1   /* the caller's order */
 #define DBSCAN_ORDER_SPATIAL 2 /* rows permuted on the device by a Morton key of their
                                   coordinates (quantised over the bounding box), so that

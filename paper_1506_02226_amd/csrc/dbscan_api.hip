@@ -22,6 +22,8 @@ constexpr uint64_t kPairsPerPoint = 128;       // default pair-list capacity per
 constexpr uint64_t kMaxPairs = 2147483647ull;  // 16 GiB of (int, int) pairs
 constexpr uint64_t kBandPerPoint = 64;         // default band-list capacity per point
 constexpr int32_t kMaxMfmaD = 76;              // contraction d + 4 <= 80
+constexpr int64_t kSpatialMinN = 65536;        // auto order: below this the sort's ~15
+                                               // launches cost more than they save
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -82,7 +84,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   const bool order_ok = d <= 4 && !mfma;
   if (o && o->reserved != 0) return DBSCAN_E_INVAL;
   if (req_order == DBSCAN_ORDER_AUTO)
-    L->order = order_ok ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
+    L->order = (order_ok && n >= kSpatialMinN) ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
   else if (req_order == DBSCAN_ORDER_INPUT)
     L->order = DBSCAN_ORDER_INPUT;
   else if (req_order == DBSCAN_ORDER_SPATIAL) {

@@ -96,7 +96,8 @@ def test_workspace_size_layout():
 
 
 def test_order_option_layout():
-    """The spatial order (default for the float32 forms at d <= 4) adds seven
+    """The spatial order (default for the float32 forms at d <= 4 from
+    n = 65536) adds seven
     n_pad-sized int32 arrays (sort keys and values, two of each; inverse
     permutation; staged-order counts; per-root label minima) and the radix
     histograms (256 per 2048-key tile); it is refused where it does not apply."""
@@ -124,6 +125,12 @@ def test_order_option_layout():
     o = _lib.make_opts("onthefly", "fp16", order="spatial")
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == \
         _lib.DBSCAN_E_UNSUPPORTED
+    small = _lib.make_opts("bitmask")
+    assert L.dbscan_workspace_size(65_535, 2, ctypes.byref(small), ctypes.byref(out)) == 0
+    auto_small = out.value
+    small.order = 1
+    assert L.dbscan_workspace_size(65_535, 2, ctypes.byref(small), ctypes.byref(out)) == 0
+    assert out.value == auto_small  # auto keeps the input order below 65536 points
     o = _lib.make_opts(order="input")
     o.order = 9
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL

@@ -42,8 +42,10 @@ def test_orders_ragged(order, n, d):
 def test_auto_order_choice():
     rng = np.random.default_rng(3)
     p2 = rng.uniform(0, 1, size=(500, 2)).astype(np.float32)
+    big = rng.uniform(0, 1, size=(70_000, 2)).astype(np.float32)
     p16 = rng.uniform(0, 1, size=(500, 16)).astype(np.float32)
-    assert run(p2, 0.05, 3, stats=True)[3]["order_used"] == "spatial"
+    assert run(p2, 0.05, 3, stats=True)[3]["order_used"] == "input"  # small n
+    assert run(big, 0.004, 3, stats=True)[3]["order_used"] == "spatial"
     assert run(p16, 0.5, 3, stats=True)[3]["order_used"] == "input"  # matrix cores
     assert run(p16, 0.5, 3, precision="fp32", stats=True)[3]["order_used"] == "input"
     with pytest.raises(pkg.DbscanError) as ei:
