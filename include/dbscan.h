@@ -70,15 +70,16 @@ extern "C" {
 
 /* Order in which the rows are processed (results are always returned in the
  * caller's order and are identical either way). */
-#define DBSCAN_ORDER_AUTO 0    /* spatial for the float32 forms with d <= 4 and
-                                  n >= 65536, else input */
+#define DBSCAN_ORDER_AUTO 0    /* spatial for d <= 128 and n >= 65536, else input */
 #define DBSCAN_ORDER_INPUT 1   /* the caller's order */
-#define DBSCAN_ORDER_SPATIAL 2 /* rows permuted on the device by a Morton key of their
-                                  coordinates (quantised over the bounding box), so that
-                                  neighbours sit at nearby indices: the sweeps meet their
-                                  rare neighbour branch far less often and the bitmask's
-                                  set bits gather near its diagonal.  float32 forms with
-                                  d <= 4 only (else DBSCAN_E_UNSUPPORTED). */
+#define DBSCAN_ORDER_SPATIAL 2 /* rows permuted on the device so that neighbours sit at
+                                  nearby indices -- by a Morton key of the coordinates
+                                  (quantised over the bounding box) for d <= 4, by the
+                                  nearest of 256 pivot rows (rows taken at a fixed
+                                  stride; 128 beyond d = 64) for 5 <= d <= 128 -- so the
+                                  sweeps meet their rare neighbour branch far less often
+                                  and the bitmask's set bits gather near its diagonal.
+                                  d <= 128 only (else DBSCAN_E_UNSUPPORTED). */
 
 /* Arithmetic of the epsilon-test filter (the decision is always float64-exact). */
 #define DBSCAN_PREC_AUTO 0 /* FP16 matrix cores for 16 <= d <= 76, else float32 */

@@ -45,11 +45,13 @@ template <> struct LowPrec<_Float16> {
 // other with the lanes over the coordinates (coalesced loads and stores):
 // rounded coordinates, the FP32 norm of the rounded point (a wave sum, split
 // hi + lo), both augmented rows, and the float64 norm of the original point
-// for the bounds (max via an atomic on its bit pattern).  K <= 128.
+// for the bounds (max via an atomic on its bit pattern).  K <= 128.  With a
+// spatial order, row i of the augmented copies is input row perm[i].
 template <typename T>
 __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, int n, int d,
                                                int n_pad, int K, T *__restrict__ a_aug,
-                                               T *__restrict__ b_aug, DevState *st, int bid) {
+                                               T *__restrict__ b_aug, DevState *st, int bid,
+                                               const int *__restrict__ perm = nullptr) {
   const int lane = lane_id();
   const int w = (int)(threadIdx.x >> 6);
   bool bad = false, nonfinite = false;
@@ -60,13 +62,14 @@ __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, in
     T *a = a_aug + (size_t)i * K;
     T *b = b_aug + (size_t)i * K;
     if (i < n) {
+      const size_t src = perm ? (size_t)perm[i] : (size_t)i;
       float part = 0.0f;
       double part64 = 0.0;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = lane + 64 * h;
         if (k < d) {
-          const float x = pts[(size_t)i * d + k];
+          const float x = pts[src * d + k];
           nonfinite |= !__builtin_isfinite(x);
           bad |= nonfinite || __builtin_fabsf(x) > LowPrec<T>::maxval;
           const T xr = (T)x;
@@ -380,7 +383,8 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
 // FP32 inputs; "in" adds to the count of column j, and also of row i when the
 // entry carries kBandBoth (a pair the sweep tested in one order only), and
 // i > j pairs go to the pair list.  This block handles band entries
-// [e_begin, e_end); `qbuf` is [4][128] pairs of LDS.
+// [e_begin, e_end); `qbuf` is [4][128] pairs of LDS.  With a spatial order
+// (perm: staged index -> input row) the rows are read through it.
 __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts, int d,
                                                    const int2 *__restrict__ band,
                                                    int *__restrict__ counts,
@@ -389,7 +393,8 @@ __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts
                                                    long long pair_cap,
                                                    unsigned long long e_begin,
                                                    unsigned long long e_end,
-                                                   int2 (*qbuf)[128]) {
+                                                   int2 (*qbuf)[128],
+                                                   const int *__restrict__ perm = nullptr) {
   const int w = wave_uniform(threadIdx.x >> 6);
   WaveQueue qp{qbuf[w], 0, 64};
   for (unsigned long long e0 = e_begin + 64ull * w; e0 < e_end; e0 += 256) {
@@ -400,7 +405,9 @@ __device__ __forceinline__ void recheck_band_range(const float *__restrict__ pts
       pr = band[e];
       const bool both = ((unsigned)pr.x & kBandBoth) != 0u;
       pr.x = (int)((unsigned)pr.x & ~kBandBoth);
-      in = exact_within_rows(pts + (size_t)pr.x * d, pts + (size_t)pr.y * d, d, eps2);
+      const size_t ra = perm ? (size_t)perm[pr.x] : (size_t)pr.x;
+      const size_t rb = perm ? (size_t)perm[pr.y] : (size_t)pr.y;
+      in = exact_within_rows(pts + ra * d, pts + rb * d, d, eps2);
       if (in) {
         atomicAdd(counts + pr.y, 1);
         if (both) atomicAdd(counts + pr.x, 1);

@@ -102,13 +102,13 @@ __global__ void k_labels(int n, const uint32_t *__restrict__ corebits,
 // When the matrix-core filter gave up: clear the counts, stage the float32
 // coordinates for the sweeps that redo step 1 (the filtered path does not
 // need them), and mark the pair list incomplete so step 3 repeats the tests.
-__global__ void k_filter_fallback(const float *__restrict__ pts, int n, int d, int n_pad,
-                                  int d_pad, float *__restrict__ soa, int *__restrict__ counts,
-                                  DevState *st) {
+__global__ void k_filter_fallback(const float *__restrict__ pts, const int *__restrict__ perm,
+                                  int n, int d, int n_pad, int d_pad, float *__restrict__ soa,
+                                  int *__restrict__ counts, DevState *st) {
   const unsigned status =
       __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!(status & (kStatusRange | kStatusBandOverflow))) return;
-  stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, blockIdx.x);
+  stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, blockIdx.x, perm);
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) counts[i] = 0;
   if (i == 0) atomicOr(&st->status, kStatusEdgeOverflow);
@@ -148,10 +148,10 @@ hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_pad, float *soa,
-                               int *counts, DevState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_filter_fallback, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, n, d,
-                     n_pad, d_pad, soa, counts, st);
+hipError_t run_filter_fallback(const float *pts, const int *perm, int n, int d, int n_pad,
+                               int d_pad, float *soa, int *counts, DevState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_fallback, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, perm, n,
+                     d, n_pad, d_pad, soa, counts, st);
   return hipGetLastError();
 }
 

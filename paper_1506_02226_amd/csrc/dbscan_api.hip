@@ -81,7 +81,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     return DBSCAN_E_INVAL;
   }
   const int req_order = o ? o->order : DBSCAN_ORDER_AUTO;
-  const bool order_ok = d <= 4 && !mfma;
+  const bool order_ok = d <= dbk::order_max_d();
   if (o && o->reserved != 0) return DBSCAN_E_INVAL;
   if (req_order == DBSCAN_ORDER_AUTO)
     L->order = (order_ok && n >= kSpatialMinN) ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
@@ -373,7 +373,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
                       st, ord, s));
   const double band_rel = (opts && opts->band_rel > 0.0) ? opts->band_rel : kDefaultBandRel;
   if (mfma) {
-    step(dbk::run_mfma_prep(points, ni, d, npad, L.precision, a_aug, b_aug, st, s));
+    step(dbk::run_mfma_prep(points, ord.perm, ni, d, npad, L.precision, a_aug, b_aug, st, s));
     step(dbk::run_mfma_thresholds(st, eps * eps, d, L.precision, band_rel, s));
   }
   mark(0);
@@ -421,7 +421,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     mark(5);
     step(dbk::run_recheck_band(points, d, bufs, eps2, L.band_cap, L.edge_cap, s));
     // the float32 sweep redoes step 1 only if the filter gave up
-    step(dbk::run_filter_fallback(points, ni, d, npad, L.d_pad, soa, counts, st, s));
+    step(dbk::run_filter_fallback(points, ord.perm, ni, d, npad, L.d_pad, soa, counts_k, st, s));
     dbk::SweepScalars f1 = sweep_tiles(sc, n, npad, d, L.d_pad);
     f1.flags = dbk::kOnlyOnFilterFail;
     step(dbk::run_count(bufs, f1, false, s));

@@ -32,7 +32,8 @@ struct Order {
   int *rootmin;     // [n] lowest caller index of the core points under each root
 };
 
-// Bits per coordinate of the spatial-order key (d <= 4; at most 32 in all).
+// Bits per coordinate of the spatial-order key for d <= 4 (at most 32 in all;
+// larger d use a pivot index, one radix pass).
 __host__ __device__ inline int order_bits_per_coord(int d) {
   return d == 1 ? 24 : (d == 2 ? 16 : (d == 3 ? 10 : 8));
 }
@@ -72,6 +73,7 @@ int coord_chunk(int d);
 
 hipError_t run_reset(DevState *st, hipStream_t s);
 long long order_hist_entries(long long n);
+int order_max_d();
 hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], int *vals[2],
                              int *hist, DevState *st, int **perm, hipStream_t s);
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
@@ -86,12 +88,12 @@ hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *co
 hipError_t run_compact_noncore(const uint32_t *corebits, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
-hipError_t run_filter_fallback(const float *pts, int n, int d, int n_pad, int d_pad, float *soa,
-                               int *counts, DevState *st, hipStream_t s);
+hipError_t run_filter_fallback(const float *pts, const int *perm, int n, int d, int n_pad,
+                               int d_pad, float *soa, int *counts, DevState *st, hipStream_t s);
 
 int mfma_k(int d);
-hipError_t run_mfma_prep(const float *pts, int n, int d, int n_pad, int prec, void *a_aug,
-                         void *b_aug, DevState *st, hipStream_t s);
+hipError_t run_mfma_prep(const float *pts, const int *perm, int n, int d, int n_pad, int prec,
+                         void *a_aug, void *b_aug, DevState *st, hipStream_t s);
 hipError_t run_mfma_thresholds(DevState *st, double eps2, int d, int prec, double band_rel,
                                hipStream_t s);
 hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b,

@@ -36,8 +36,9 @@ namespace dbk {
 // ---------------------------------------------------------------- prepare
 template <typename T>
 __global__ void k_mfma_prep(const float *__restrict__ pts, int n, int d, int n_pad, int K,
-                            T *__restrict__ a_aug, T *__restrict__ b_aug, DevState *st) {
-  mfma_prep_body<T>(pts, n, d, n_pad, K, a_aug, b_aug, st, blockIdx.x);
+                            T *__restrict__ a_aug, T *__restrict__ b_aug, DevState *st,
+                            const int *__restrict__ perm) {
+  mfma_prep_body<T>(pts, n, d, n_pad, K, a_aug, b_aug, st, blockIdx.x, perm);
 }
 
 // ------------------------------------------------------------- thresholds
@@ -65,7 +66,8 @@ __global__ __launch_bounds__(256) void k_recheck_band(const float *__restrict__ 
                                                       int *__restrict__ counts,
                                                       int2 *__restrict__ pairs,
                                                       DevState *__restrict__ st, double eps2,
-                                                      long long band_cap, long long pair_cap) {
+                                                      long long band_cap, long long pair_cap,
+                                                      const int *__restrict__ perm) {
   __shared__ int2 qbuf[4][128];
   const unsigned status =
       __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -76,23 +78,23 @@ __global__ __launch_bounds__(256) void k_recheck_band(const float *__restrict__ 
   const unsigned long long per = (total + gridDim.x - 1) / gridDim.x;
   const unsigned long long b = (unsigned long long)blockIdx.x * per;
   const unsigned long long e = b + per < total ? b + per : total;
-  recheck_band_range(pts, d, band, counts, pairs, st, eps2, pair_cap, b, e, qbuf);
+  recheck_band_range(pts, d, band, counts, pairs, st, eps2, pair_cap, b, e, qbuf, perm);
   if (threadIdx.x == 0 && blockIdx.x == 0) atomicAdd(&st->band_pairs, total);
 }
 
 // ------------------------------------------------------------ host launchers
 int mfma_k(int d) { return (d + 4 + 15) / 16 * 16; }
 
-hipError_t run_mfma_prep(const float *pts, int n, int d, int n_pad, int prec, void *a_aug,
-                         void *b_aug, DevState *st, hipStream_t s) {
+hipError_t run_mfma_prep(const float *pts, const int *perm, int n, int d, int n_pad, int prec,
+                         void *a_aug, void *b_aug, DevState *st, hipStream_t s) {
   const int K = mfma_k(d);
   const dim3 grid((n_pad + 255) / 256), block(256);
   if (prec == kPrecBf16)
     hipLaunchKernelGGL(k_mfma_prep<__bf16>, grid, block, 0, s, pts, n, d, n_pad, K,
-                       (__bf16 *)a_aug, (__bf16 *)b_aug, st);
+                       (__bf16 *)a_aug, (__bf16 *)b_aug, st, perm);
   else
     hipLaunchKernelGGL(k_mfma_prep<_Float16>, grid, block, 0, s, pts, n, d, n_pad, K,
-                       (_Float16 *)a_aug, (_Float16 *)b_aug, st);
+                       (_Float16 *)a_aug, (_Float16 *)b_aug, st, perm);
   return hipGetLastError();
 }
 
@@ -141,7 +143,7 @@ hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b
 hipError_t run_recheck_band(const float *pts, int d, const Buffers &b, double eps2,
                             long long band_cap, long long pair_cap, hipStream_t s) {
   hipLaunchKernelGGL(k_recheck_band, dim3(1024), dim3(256), 0, s, pts, d, b.band, b.counts,
-                     b.pairs, b.st, eps2, band_cap, pair_cap);
+                     b.pairs, b.st, eps2, band_cap, pair_cap, b.okey);
   return hipGetLastError();
 }
 

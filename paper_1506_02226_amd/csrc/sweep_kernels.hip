@@ -333,6 +333,9 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
 enum { MODE_COUNT = 0, MODE_UNION = 1, MODE_BORDER = 2 };
 
 // One block's work (`bid` = its index in the full grid).
+// With a spatial order (okey: caller's index of each staged row), the border
+// mode takes the smallest okey over all the core neighbours instead of the
+// first one in staged order.
 template <int DC, int R, int MODE>
 __device__ __forceinline__ void rows_lds_block(const float *__restrict__ soa,
                                                int *__restrict__ counts,
@@ -340,6 +343,7 @@ __device__ __forceinline__ void rows_lds_block(const float *__restrict__ soa,
                                                int *__restrict__ parent,
                                                const int *__restrict__ list,
                                                int *__restrict__ jstar,
+                                               const int *__restrict__ okey,
                                                DevState *__restrict__ st, const SweepScalars &sc,
                                                float *lds_rows, int bid) {
   const int lane = lane_id();
@@ -449,8 +453,13 @@ __device__ __forceinline__ void rows_lds_block(const float *__restrict__ soa,
       } else if (MODE == MODE_UNION) {
         if ((in >> lane) & 1ull) uf_union(parent, rows[r], j);
       } else if (in != 0ull) {
-        acc[r] = cb + __builtin_ctzll(in);
-        active &= ~(1u << r);
+        if (okey) {
+          for (uint64_t m2 = in; m2 != 0ull; m2 &= m2 - 1ull)
+            acc[r] = min(acc[r], okey[cb + __builtin_ctzll(m2)]);
+        } else {
+          acc[r] = cb + __builtin_ctzll(in);
+          active &= ~(1u << r);
+        }
       }
     }
   }
@@ -484,12 +493,14 @@ __global__ __launch_bounds__(256) void k_rows_lds(const float *__restrict__ soa,
                                                   int *__restrict__ parent,
                                                   const int *__restrict__ list,
                                                   int *__restrict__ jstar,
+                                                  const int *__restrict__ okey,
                                                   DevState *__restrict__ st, SweepScalars sc,
                                                   int nblocks) {
   extern __shared__ float lds_rows[];
   if (skip_sweep(sc, st)) return;
   for (int bid = blockIdx.x; bid < nblocks; bid += gridDim.x) {
-    rows_lds_block<DC, R, MODE>(soa, counts, corebits, parent, list, jstar, st, sc, lds_rows, bid);
+    rows_lds_block<DC, R, MODE>(soa, counts, corebits, parent, list, jstar, okey, st, sc,
+                                lds_rows, bid);
     __syncthreads();
   }
 }
@@ -517,8 +528,8 @@ static hipError_t launch_lds(const Buffers &b, const SweepScalars &sc, int block
 #define DBK_LDS_CASE(DC)                                                                      \
   case DC:                                                                                    \
     hipLaunchKernelGGL((k_rows_lds<DC, kRowsLds, MODE>), dim3(grid), dim3(256), lds, s,      \
-                       b.soa, b.counts, b.corebits, b.parent, b.list, b.jstar, b.st, sc,      \
-                       blocks);                                                               \
+                       b.soa, b.counts, b.corebits, b.parent, b.list, b.jstar, b.okey, b.st,  \
+                       sc, blocks);                                                           \
     break;
     DBK_LDS_CASE(8)
     DBK_LDS_CASE(16)

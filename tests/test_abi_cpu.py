@@ -79,13 +79,13 @@ def test_workspace_size_layout():
     small = _lib.make_opts("onthefly", pair_capacity=1000)
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(small), ctypes.byref(out)) == 0
     assert out.value == base + 8 * 1024  # 1000 pairs, rounded up to 256 bytes
-    wide = _lib.make_opts("onthefly", "fp32")  # d > 4 in float32: pair list too
+    wide = _lib.make_opts("onthefly", "fp32", order="input")  # d > 4 in float32: pair list too
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(wide), ctypes.byref(out)) == 0
     assert 8 * 128 * 100_000 < out.value < 8 * 128 * 100_000 + 32 * 100_096 * 4
     plain = out.value
     # matrix cores (auto for 16 <= d <= 76): + two augmented copies (K = 32 here,
     # 2 bytes each) and 64 band entries per point, 8 bytes each
-    mc = _lib.make_opts("onthefly", "auto")
+    mc = _lib.make_opts("onthefly", "auto", order="input")
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(mc), ctypes.byref(out)) == 0
     extra = 2 * 100_096 * 32 * 2 + 8 * 64 * 100_000
     assert out.value - plain == extra
@@ -96,8 +96,7 @@ def test_workspace_size_layout():
 
 
 def test_order_option_layout():
-    """The spatial order (default for the float32 forms at d <= 4 from
-    n = 65536) adds seven
+    """The spatial order (default for d <= 128 from n = 65536) adds seven
     n_pad-sized int32 arrays (sort keys and values, two of each; inverse
     permutation; staged-order counts; per-root label minima) and the radix
     histograms (256 per 2048-key tile); it is refused where it does not apply."""
@@ -119,12 +118,19 @@ def test_order_option_layout():
     for adj in ("bitmask", "onthefly"):
         assert size(adjacency=adj, order="spatial") - size(adjacency=adj, order="input") == extra
         assert size(adjacency=adj) == size(adjacency=adj, order="spatial")  # auto
+    # d > 4 (pivot order, one radix pass) up to d = 128, matrix cores included
+    for d in (5, 128):
+        o = _lib.make_opts("onthefly", "fp32", order="spatial")
+        assert L.dbscan_workspace_size(1000, d, ctypes.byref(o), ctypes.byref(out)) == 0
     o = _lib.make_opts("onthefly", "fp32", order="spatial")
-    assert L.dbscan_workspace_size(1000, 5, ctypes.byref(o), ctypes.byref(out)) == \
+    assert L.dbscan_workspace_size(1000, 129, ctypes.byref(o), ctypes.byref(out)) == \
         _lib.DBSCAN_E_UNSUPPORTED
-    o = _lib.make_opts("onthefly", "fp16", order="spatial")
-    assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == \
-        _lib.DBSCAN_E_UNSUPPORTED
+    sizes = {}
+    for order in ("input", "spatial"):
+        o = _lib.make_opts("onthefly", "fp16", order=order)
+        assert L.dbscan_workspace_size(n, 64, ctypes.byref(o), ctypes.byref(out)) == 0
+        sizes[order] = out.value
+    assert sizes["spatial"] - sizes["input"] == extra
     small = _lib.make_opts("bitmask")
     assert L.dbscan_workspace_size(65_535, 2, ctypes.byref(small), ctypes.byref(out)) == 0
     auto_small = out.value

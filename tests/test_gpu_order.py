@@ -22,9 +22,18 @@ MODES = ("bitmask", "onthefly")
 ORDERS = ("input", "spatial")
 
 
+def forms(d):
+    """(adjacency, precision) pairs that apply at dimension d."""
+    if d <= 4:
+        return [("bitmask", "fp32"), ("onthefly", "fp32")]
+    if d < 16:
+        return [("onthefly", "fp32")]
+    return [("onthefly", "fp32"), ("onthefly", "fp16"), ("onthefly", "bf16")]
+
+
 @pytest.mark.parametrize("order", ORDERS)
 @pytest.mark.parametrize("n", [1, 2, 65, 257, 2049, 4099])
-@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 16, 64])
 def test_orders_ragged(order, n, d):
     rng = np.random.default_rng(7000 * n + d)
     k = max(1, n // 40)
@@ -33,10 +42,10 @@ def test_orders_ragged(order, n, d):
     eps = float(0.35 * np.sqrt(d))
     minpts = int(rng.integers(1, 8))
     ref = orc.dbscan(pts, eps, minpts)
-    for mode in MODES:
-        gpu = run(pts, eps, minpts, adjacency=mode, order=order, stats=True)
+    for adj, prec in forms(d):
+        gpu = run(pts, eps, minpts, adjacency=adj, precision=prec, order=order, stats=True)
         assert gpu[3]["order_used"] == order
-        assert_same(gpu, ref, f"n={n} d={d} {mode} {order}")
+        assert_same(gpu, ref, f"n={n} d={d} {adj} {prec} {order}")
 
 
 def test_auto_order_choice():
@@ -46,10 +55,13 @@ def test_auto_order_choice():
     p16 = rng.uniform(0, 1, size=(500, 16)).astype(np.float32)
     assert run(p2, 0.05, 3, stats=True)[3]["order_used"] == "input"  # small n
     assert run(big, 0.004, 3, stats=True)[3]["order_used"] == "spatial"
-    assert run(p16, 0.5, 3, stats=True)[3]["order_used"] == "input"  # matrix cores
-    assert run(p16, 0.5, 3, precision="fp32", stats=True)[3]["order_used"] == "input"
+    assert run(p16, 0.5, 3, stats=True)[3]["order_used"] == "input"  # small n
+    big16 = rng.uniform(0, 1, size=(70_000, 16)).astype(np.float32)
+    st = run(big16, 0.3, 3, stats=True)[3]
+    assert st["order_used"] == "spatial" and st["precision_used"] == "fp16"
+    p130 = rng.uniform(0, 1, size=(300, 130)).astype(np.float32)
     with pytest.raises(pkg.DbscanError) as ei:
-        run(p16, 0.5, 3, precision="fp32", order="spatial")
+        run(p130, 0.5, 3, order="spatial")
     assert ei.value.code == pkg._lib.DBSCAN_E_UNSUPPORTED
 
 
@@ -105,11 +117,31 @@ def test_spatial_order_nonfinite_reported():
         assert (lab == -2).all()
 
 
-@pytest.mark.parametrize("name,n", [("blobs2d_200k", 30_000), ("aniso3d_2m", 30_000)])
+@pytest.mark.parametrize("name,n", [("blobs2d_200k", 30_000), ("aniso3d_2m", 30_000),
+                                    ("mix64d_300k_q50", 6_000), ("mix64d_300k", 6_000)])
 def test_orders_scaled_recipes(name, n):
     w = wl.by_name(name, 0, n)
     ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
-    for mode in MODES:
+    for adj, prec in forms(w.d):
         for order in ORDERS:
-            assert_same(run(w.points, w.eps, w.minpts, adjacency=mode, order=order), ref,
-                        f"{name} {mode} {order}")
+            assert_same(run(w.points, w.eps, w.minpts, adjacency=adj, precision=prec, order=order),
+                        ref, f"{name} {adj} {prec} {order}")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_pivot_order_fallbacks(prec):
+    """d > 4 in spatial order through the fallbacks: pair-list overflow (the
+    merge and the border pass repeat the tests, keyed by caller index) and,
+    for the matrix cores, band-list overflow (step 1 redone in float32 from
+    the points in staged order)."""
+    w = wl.by_name("mix64d_300k_q50", 0, 6_000)
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    gpu = run(w.points, w.eps, w.minpts, adjacency="onthefly", precision=prec, order="spatial",
+              pair_capacity=1, stats=True)
+    assert gpu[3]["pair_overflow"] == 1
+    assert_same(gpu, ref, f"{prec} pair overflow")
+    if prec == "fp16":
+        gpu = run(w.points, w.eps, w.minpts, adjacency="onthefly", precision=prec,
+                  order="spatial", band_capacity=1, stats=True)
+        assert gpu[3]["filter_fallback"] == 1
+        assert_same(gpu, ref, "band overflow")
