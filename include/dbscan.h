@@ -117,7 +117,13 @@ typedef struct dbscan_opts {
                                  band pass), so the caller can time the kernels of
                                  a call it does not wait for. */
   int32_t order;              /* DBSCAN_ORDER_* (0 = auto) */
-  int32_t reserved;           /* must be 0 */
+  int32_t prune;              /* 1: skip the epsilon tests of tile pairs whose bounding
+                                 boxes are farther apart than eps (float32 forms,
+                                 d <= 4; effective with the spatial order).  The
+                                 results are identical -- a skipped pair is provably
+                                 not a neighbour -- but not every pair is tested, so
+                                 sweep1_tests then counts the tests actually made.
+                                 0 (default): every pair is tested. */
 } dbscan_opts;
 
 typedef struct dbscan_stats {
@@ -145,9 +151,10 @@ typedef struct dbscan_stats {
                              triangular float32 sweeps (each unordered pair
                              once, both orders inside 64x64 diagonal blocks)
                              and for the matrix-core tiles (256x256 diagonal
-                             zones) */
+                             zones); with pruning, the tests made (counted on
+                             the device) */
   int32_t order_used;     /* DBSCAN_ORDER_INPUT or DBSCAN_ORDER_SPATIAL */
-  int32_t reserved;
+  int32_t pruned;         /* 1 if tile pruning was on (dbscan_opts.prune) */
 } dbscan_stats;
 
 /*

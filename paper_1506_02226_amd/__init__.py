@@ -29,10 +29,11 @@ def version() -> int:
 
 def workspace_size(n: int, d: int, adjacency: str = "auto", precision: str = "auto",
                    bitmask_limit: int = 0, pair_capacity: int = 0, band_capacity: int = 0,
-                   order: str = "auto") -> int:
+                   order: str = "auto", prune: bool = False) -> int:
     L = _lib.load()
     opts = _lib.make_opts(adjacency, precision, bitmask_limit=bitmask_limit,
-                          pair_capacity=pair_capacity, band_capacity=band_capacity, order=order)
+                          pair_capacity=pair_capacity, band_capacity=band_capacity, order=order,
+                          prune=prune)
     out = ctypes.c_uint64(0)
     rc = L.dbscan_workspace_size(int(n), int(d), ctypes.byref(opts), ctypes.byref(out))
     if rc != _lib.DBSCAN_OK:
@@ -54,7 +55,7 @@ def _check_points(points):
 def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: str = "auto",
         band_rel: float = 0.0, bitmask_limit: int = 0, pair_capacity: int = 0,
         band_capacity: int = 0, stats: bool = False, out=None, workspace=None, events: int = 0,
-        order: str = "auto"):
+        order: str = "auto", prune: bool = False):
     """Cluster `points` (torch float32 (n, d) on the GPU).
 
     Returns (labels int32[n], core uint8[n], counts int32[n]) as GPU tensors,
@@ -63,7 +64,9 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
     ``workspace`` a uint8 GPU tensor of at least ``workspace_size`` bytes.
     ``events`` is the address of a caller-created hipEvent_t[6] that the
     library records around the steps (see dbscan_opts.events).  ``order``
-    is "auto", "input" or "spatial" (dbscan_opts.order)."""
+    is "auto", "input" or "spatial" (dbscan_opts.order); ``prune`` skips
+    the tests of tile pairs whose boxes are farther apart than eps
+    (dbscan_opts.prune)."""
     import torch
     L = _lib.load()
     x = _check_points(points)
@@ -76,14 +79,14 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
     else:
         labels, core, counts = out
     ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit, pair_capacity,
-                              band_capacity, order)
+                              band_capacity, order, prune)
     if workspace is None:
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) // 256 * 256
     avail = workspace.numel() - (aligned - base)
     opts = _lib.make_opts(adjacency, precision, band_rel, bitmask_limit, aligned, avail, events,
-                          pair_capacity, band_capacity, order)
+                          pair_capacity, band_capacity, order, prune)
     st = _lib.Stats()
     stream = torch.cuda.current_stream(dev).cuda_stream
     with torch.cuda.device(dev):

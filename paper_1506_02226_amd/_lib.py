@@ -59,7 +59,7 @@ class Opts(ctypes.Structure):
         ("band_capacity", ctypes.c_uint64),
         ("events", ctypes.c_void_p),
         ("order", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("prune", ctypes.c_int32),
     ]
 
 
@@ -84,7 +84,7 @@ class Stats(ctypes.Structure):
         ("ms_sweep1", ctypes.c_float),
         ("sweep1_tests", ctypes.c_int64),
         ("order_used", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("pruned", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -204,7 +204,7 @@ def load(path: str | None = None):
 def make_opts(adjacency: str = "auto", precision: str = "auto", band_rel: float = 0.0,
               bitmask_limit: int = 0, workspace: int = 0, workspace_bytes: int = 0,
               events: int = 0, pair_capacity: int = 0, band_capacity: int = 0,
-              order: str = "auto") -> Opts:
+              order: str = "auto", prune: bool = False) -> Opts:
     return Opts(ADJ[adjacency], PREC[precision], float(band_rel), int(bitmask_limit),
                 int(workspace) or None, int(workspace_bytes), int(pair_capacity),
-                int(band_capacity), int(events) or None, ORDER[order], 0)
+                int(band_capacity), int(events) or None, ORDER[order], 1 if prune else 0)

@@ -42,7 +42,12 @@ namespace dbk {
 constexpr int kBitmaskMaxChunk = 4096;
 constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 
-template <int D>
+// PRUNE (rows in spatial order; not the paper's all-pairs sweep, so reported
+// apart): blocks and 32 x 64 tiles whose row and column boxes are farther
+// apart than eps (box_gap2 > hi) are skipped and left flagged empty (a wave
+// tests the 64 column boxes of its chunk at once, one per lane, and visits
+// only the blocks within reach); the tests actually made go to st->tests.
+template <int D, bool PRUNE>
 __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
                                                  uint32_t *__restrict__ adj,
                                                  uint8_t *__restrict__ tflag,
@@ -58,9 +63,26 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
   const int c0 = chunk * sc.chunk;
   const int c1 = min(c0 + sc.chunk, sc.n_pad);
   if (g0 >= sc.n_pad || c1 <= g0) return;  // block-uniform
-  for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
-  __syncthreads();
   const int g1 = min(g0 + sc.rgroup, sc.n_pad);
+  const int nq = sc.n_pad / 32, nb = sc.n_pad / 64;
+  // PRUNE: lane l holds the box of column block c0 / 64 + l (a chunk has at
+  // most 64 of them), read back with a lane read when the wave reaches it
+  float lbl[D], lbh[D];
+  if (PRUNE) {
+    // every wave derives the same boxes, so the exit is block-uniform (the
+    // flags were cleared beforehand, so a skipped block leaves its tiles empty)
+    float rlo[D], rhi[D], clo[D], chi[D];
+    span_box<D>(sc.box, nb, g0 / 64, g1 / 64, rlo, rhi);
+    lane_box<D>(sc.box, nb, c0 / 64, c1 / 64, lbl, lbh);
+    wave_box<D>(lbl, lbh, clo, chi);
+    if (box_gap2<D>(rlo, rhi, clo, chi) > sc.hi) return;
+  }
+  for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
+  if (PRUNE)  // tiles a wave does not visit stay empty
+    for (int t = threadIdx.x; t < (kBitmaskMaxRows / 32) * (kBitmaskMaxChunk / 64); t += 256)
+      tiles[t / (kBitmaskMaxChunk / 64)][t % (kBitmaskMaxChunk / 64)] = 0;
+  __syncthreads();
+  unsigned long long tested = 0;  // PRUNE: pair tests made by this wave
   for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
@@ -76,17 +98,21 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
     for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
     uint32_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
     uint8_t *flag = tiles[(row0 - g0) / R];  // [column block - c0 / 64]
-    float xn[D];
+    float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
+    if (PRUNE) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
-    for (int cb = cs; cb < c1; cb += 64) {
-      float xc[D];
+      for (int k = 0; k < D; ++k) {
+        rlo[k] = xr[0][k];
+        rhi[k] = xr[0][k];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xc[k] = xn[k];
-      if (cb + 64 < c1) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+        for (int r = 1; r < R; ++r) {
+          rlo[k] = __builtin_fminf(rlo[k], xr[r][k]);
+          rhi[k] = __builtin_fmaxf(rhi[k], xr[r][k]);
+        }
       }
+    }
+    // the tests of the R rows against the 64 columns cb .. cb + 63 (coordinates xc)
+    auto tile = [&](int cb, const float (&xc)[D]) {
       uint32_t word = 0;
       // rows in groups of G: the common case (no neighbour among the 64
       // columns for any of the G rows) costs one compare of the group's
@@ -116,6 +142,46 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
       const bool filled = __ballot(word != 0u) != 0ull;
       if (lane == 0) flag[(cb - c0) >> 6] = filled ? 1 : 0;
       if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
+    };
+    float xn[D];
+    if (PRUNE) {
+      // the column blocks within reach of the rows' box: one test per lane
+      // (lane l against column block c0 / 64 + l), then only those blocks;
+      // the others keep the empty flag set when the block started
+      const int cbl = c0 + 64 * lane;
+      uint64_t cand = __ballot(cbl >= cs && cbl < c1 && box_gap2<D>(rlo, rhi, lbl, lbh) <= sc.hi);
+      tested += (unsigned long long)__popcll(cand) * R * 64;
+      if (cand != 0ull) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          xn[k] = soa[(size_t)k * sc.n_pad + c0 + 64 * __builtin_ctzll(cand) + lane];
+      }
+      while (cand != 0ull) {
+        const int cb = c0 + 64 * __builtin_ctzll(cand);
+        cand &= cand - 1ull;
+        float xc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xc[k] = xn[k];
+        if (cand != 0ull) {
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+            xn[k] = soa[(size_t)k * sc.n_pad + c0 + 64 * __builtin_ctzll(cand) + lane];
+        }
+        tile(cb, xc);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+      for (int cb = cs; cb < c1; cb += 64) {
+        float xc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xc[k] = xn[k];
+        if (cb + 64 < c1) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+        }
+        tile(cb, xc);
+      }
     }
     int mine = 0;
 #pragma unroll
@@ -124,6 +190,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
     const int row = row0 + lane;
     if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
   }
+  if (PRUNE && lane == 0 && tested) atomicAdd(&st->tests, tested);
   __syncthreads();
   for (int t = threadIdx.x; t < c1 - c0; t += 256) {
     const int v = colcnt[t];
@@ -131,7 +198,7 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
   }
   // flags of the tiles this block computed: 32-row block q, column block
   // cb >= the diagonal block of q's rows
-  const int nq = sc.n_pad / 32, nr = (g1 - g0) / 32, nc = (c1 - c0) / 64;
+  const int nr = (g1 - g0) / 32, nc = (c1 - c0) / 64;
   for (int t = threadIdx.x; t < nr * nc; t += 256) {
     const int rr = t % nr, cc = t / nr;
     const int q = g0 / 32 + rr, cb = c0 + 64 * cc;
@@ -336,6 +403,13 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   wq_drain_union(qu, parent, true);
 }
 
+// Tile flags cleared before a pruned sweep (16-byte stores).
+__global__ __launch_bounds__(256) void k_clear_flags(uint4 *__restrict__ p, long long n16) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n16;
+       i += (long long)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // ------------------------------------------------------------ host launchers
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   if (sc.chunk % 64 != 0 || sc.chunk > kBitmaskMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0 ||
@@ -343,13 +417,29 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
     return hipErrorInvalidValue;
   const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
   const dim3 grid(groups * sc.nchunks), block(256);
+  if (sc.box) {
+    // n_pad is a multiple of 256, so the flags are whole 16-byte pieces
+    const long long n16 = (long long)(sc.n_pad / 64) * (sc.n_pad / 32) / 16;
+    hipLaunchKernelGGL(k_clear_flags, dim3(n16 < 4096 * 256 ? (unsigned)((n16 + 255) / 256) : 4096),
+                       dim3(256), 0, s, (uint4 *)b.tflag, n16);
+  }
+#define DBK_BITMASK(D)                                                                        \
+  case D:                                                                                     \
+    if (sc.box)                                                                               \
+      hipLaunchKernelGGL((k_bitmask<D, true>), grid, block, 0, s, b.soa, (uint32_t *)b.adjT,  \
+                         b.tflag, b.counts, b.st, sc);                                        \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_bitmask<D, false>), grid, block, 0, s, b.soa, (uint32_t *)b.adjT, \
+                         b.tflag, b.counts, b.st, sc);                                        \
+    break;
   switch (sc.d) {
-    case 1: hipLaunchKernelGGL(k_bitmask<1>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
-    case 2: hipLaunchKernelGGL(k_bitmask<2>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
-    case 3: hipLaunchKernelGGL(k_bitmask<3>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
-    case 4: hipLaunchKernelGGL(k_bitmask<4>, grid, block, 0, s, b.soa, (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc); break;
+    DBK_BITMASK(1)
+    DBK_BITMASK(2)
+    DBK_BITMASK(3)
+    DBK_BITMASK(4)
     default: return hipErrorInvalidValue;
   }
+#undef DBK_BITMASK
   return hipGetLastError();
 }
 

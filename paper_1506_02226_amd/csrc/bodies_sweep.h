@@ -26,7 +26,15 @@ __device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const f
 // `colcnt` (LDS, sc.chunk entries) and added to counts[] at the end.  In the
 // diagonal 64x64 block every row visits all 64 columns itself, so there the
 // column tally is not taken, and only pairs below the diagonal are listed.
-template <int D, int R, bool EMIT>
+//
+// PRUNE (rows in spatial order; not the paper's all-pairs sweep, so reported
+// apart): a block whose rows and columns have boxes farther apart than eps
+// (box_gap2 > hi over the 64-point block boxes sc.box) returns at once, and a
+// wave visits only the 64-column blocks whose box is within reach of its R
+// rows' box (all 64 blocks of the chunk tested at once, one per lane).
+// Skipped pairs are provably not neighbours; the tests actually made go to
+// st->tests.
+template <int D, int R, bool EMIT, bool PRUNE = false>
 __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
                                                int *__restrict__ counts,
                                                int2 *__restrict__ pairs,
@@ -41,10 +49,23 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
   const int c0 = chunk * sc.chunk;
   const int c1 = min(c0 + sc.chunk, sc.n_pad);
   if (g0 >= sc.n || c1 <= g0) return;  // block-uniform
+  const int g1 = min(g0 + sc.rgroup, sc.n);
+  const int nb = sc.n_pad / 64;
+  // PRUNE: lane l holds the box of column block c0 / 64 + l (a chunk has at
+  // most 64 of them), read back with a lane read when the wave reaches it
+  float lbl[D], lbh[D];
+  if (PRUNE) {
+    // every wave derives the same boxes, so the exit is block-uniform
+    float rlo[D], rhi[D], clo[D], chi[D];
+    span_box<D>(sc.box, nb, g0 / 64, (g1 + 63) / 64, rlo, rhi);
+    lane_box<D>(sc.box, nb, c0 / 64, c1 / 64, lbl, lbh);
+    wave_box<D>(lbl, lbh, clo, chi);
+    if (box_gap2<D>(rlo, rhi, clo, chi) > sc.hi) return;
+  }
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
   __syncthreads();
-  const int g1 = min(g0 + sc.rgroup, sc.n);
   WaveQueue qu{qbuf[w], 0, kListDrain};
+  unsigned long long tested = 0;  // PRUNE: pair tests made by this wave
   for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
@@ -57,17 +78,21 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     int cnt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) cnt[r] = 0;
-    float xn[D];
+    float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
+    if (PRUNE) {
 #pragma unroll
-    for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
-    for (int cb = cs; cb < c1; cb += 64) {
-      float xc[D];
+      for (int k = 0; k < D; ++k) {
+        rlo[k] = xr[0][k];
+        rhi[k] = xr[0][k];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xc[k] = xn[k];
-      if (cb + 64 < c1) {
-#pragma unroll
-        for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+        for (int r = 1; r < R; ++r) {
+          rlo[k] = __builtin_fminf(rlo[k], xr[r][k]);
+          rhi[k] = __builtin_fmaxf(rhi[k], xr[r][k]);
+        }
       }
+    }
+    // the tests of the R rows against the 64 columns cb .. cb + 63 (coordinates xc)
+    auto tile = [&](int cb, const float (&xc)[D]) {
       const bool off = cb != diag;
       uint32_t tally = 0;
       // rows in groups of GR: one compare of their minimum and one branch
@@ -103,6 +128,45 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
         }
       }
       if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
+    };
+    float xn[D];
+    if (PRUNE) {
+      // the column blocks within reach of the rows' box: one test per lane
+      // (lane l against column block c0 / 64 + l), then only those blocks
+      const int cbl = c0 + 64 * lane;
+      uint64_t cand = __ballot(cbl >= cs && cbl < c1 && box_gap2<D>(rlo, rhi, lbl, lbh) <= sc.hi);
+      tested += (unsigned long long)__popcll(cand) * R * 64;
+      if (cand != 0ull) {
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          xn[k] = soa[(size_t)k * sc.n_pad + c0 + 64 * __builtin_ctzll(cand) + lane];
+      }
+      while (cand != 0ull) {
+        const int cb = c0 + 64 * __builtin_ctzll(cand);
+        cand &= cand - 1ull;
+        float xc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xc[k] = xn[k];
+        if (cand != 0ull) {
+#pragma unroll
+          for (int k = 0; k < D; ++k)
+            xn[k] = soa[(size_t)k * sc.n_pad + c0 + 64 * __builtin_ctzll(cand) + lane];
+        }
+        tile(cb, xc);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+      for (int cb = cs; cb < c1; cb += 64) {
+        float xc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) xc[k] = xn[k];
+        if (cb + 64 < c1) {
+#pragma unroll
+          for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+        }
+        tile(cb, xc);
+      }
     }
     int mine = 0;
 #pragma unroll
@@ -111,6 +175,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     const int row = row0 + lane;
     if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
   }
+  if (PRUNE && lane == 0 && tested) atomicAdd(&st->tests, tested);
   if (EMIT) wq_flush_block(qu, pairs, sc.edge_cap, &st->edges, &st->status, kStatusEdgeOverflow, xfer);
   __syncthreads();
   for (int t = threadIdx.x; t < c1 - c0; t += 256) {

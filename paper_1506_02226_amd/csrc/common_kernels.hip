@@ -24,6 +24,7 @@ __global__ void k_reset_state(DevState *st) {
       st->box_lo[k] = ~0u;
       st->box_hi[k] = 0u;
     }
+    st->tests = 0;
   }
 }
 
@@ -114,7 +115,35 @@ __global__ void k_filter_fallback(const float *__restrict__ pts, const int *__re
   if (i == 0) atomicOr(&st->status, kStatusEdgeOverflow);
 }
 
+// --------------------------------------------------------- block boxes
+// Box of each 64-point block of the staged coordinates (d <= 4): one wave per
+// block, NaN padding ignored; an empty block gets lo = +inf, hi = -inf.
+__global__ __launch_bounds__(256) void k_block_boxes(const float *__restrict__ soa, int n_pad,
+                                                     int d, float *__restrict__ box) {
+  const int nb = n_pad / 64;
+  const int b = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (b >= nb) return;
+  for (int k = 0; k < d; ++k) {
+    const float v = soa[(size_t)k * n_pad + b * 64 + lane_id()];
+    float l = v, h = v;
+    for (int off = 32; off > 0; off >>= 1) {
+      l = __builtin_fminf(l, __shfl_xor(l, off));
+      h = __builtin_fmaxf(h, __shfl_xor(h, off));
+    }
+    if (lane_id() == 0) {
+      box[(size_t)(2 * k) * nb + b] = (l == l) ? l : __builtin_inff();
+      box[(size_t)(2 * k + 1) * nb + b] = (h == h) ? h : -__builtin_inff();
+    }
+  }
+}
+
 // ------------------------------------------------------------ host launchers
+hipError_t run_block_boxes(const float *soa, int n_pad, int d, float *box, hipStream_t s) {
+  const int nb = n_pad / 64;
+  hipLaunchKernelGGL(k_block_boxes, dim3((nb + 3) / 4), dim3(256), 0, s, soa, n_pad, d, box);
+  return hipGetLastError();
+}
+
 hipError_t run_reset(DevState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();

@@ -33,6 +33,7 @@ struct Layout {
   int adjacency = DBSCAN_ADJ_ONTHEFLY;
   int precision = DBSCAN_PREC_FP32;
   int order = DBSCAN_ORDER_INPUT;
+  bool prune = false;
   uint64_t off_state = 0, off_soa = 0, off_parent = 0, off_jstar = 0, off_corebits = 0,
            off_list = 0, off_adj = 0, off_tflag = 0, off_pairs = 0, off_aaug = 0, off_baug = 0, off_band = 0,
            total = 0;
@@ -40,6 +41,7 @@ struct Layout {
   // the inverse permutation, staged-order counts and per-root label minima
   uint64_t off_keys[2] = {0, 0}, off_vals[2] = {0, 0}, off_hist = 0, off_inv = 0,
            off_counts = 0, off_rootmin = 0;
+  uint64_t off_box = 0;  // tile pruning: per-64-point-block boxes
   int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4 or matrix cores)
   int64_t band_cap = 0;  // band-list entries (matrix cores)
   int mfma_k = 0;        // contraction length of the matrix-core filter
@@ -82,7 +84,12 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   }
   const int req_order = o ? o->order : DBSCAN_ORDER_AUTO;
   const bool order_ok = d <= dbk::order_max_d();
-  if (o && o->reserved != 0) return DBSCAN_E_INVAL;
+  const int req_prune = o ? o->prune : 0;
+  if (req_prune != 0 && req_prune != 1) return DBSCAN_E_INVAL;
+  if (req_prune) {
+    if (d > 4 || mfma) return DBSCAN_E_UNSUPPORTED;
+    L->prune = true;
+  }
   if (req_order == DBSCAN_ORDER_AUTO)
     L->order = (order_ok && n >= kSpatialMinN) ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
   else if (req_order == DBSCAN_ORDER_INPUT)
@@ -129,6 +136,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     L->off_counts = take((uint64_t)L->n_pad * 4);
     L->off_rootmin = take((uint64_t)L->n_pad * 4);
   }
+  if (L->prune) L->off_box = take((uint64_t)2 * d * (L->n_pad / 64) * 4);
   L->total = off;
   return DBSCAN_OK;
 }
@@ -401,6 +409,12 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   sc.eps2 = eps2;
   sc.edge_cap = L.edge_cap;
   sc.flags = 0;
+  sc.box = nullptr;
+  if (L.prune) {
+    float *box = (float *)(ws + L.off_box);
+    step(dbk::run_block_boxes(soa, npad, d, box, s));
+    sc.box = box;
+  }
   const bool use_pairs = L.edge_cap > 0;
 
   // ---- step 1 (+ the neighbour counts of step 2)
@@ -521,7 +535,10 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   stats->thr_lo = mfma ? hst.thr[0] : lo;
   stats->thr_hi = mfma ? hst.thr[1] : hi;
   stats->ms_sweep1 = t45;
-  stats->sweep1_tests = sweep_tests(n, L.n_pad, d, L.adjacency == DBSCAN_ADJ_BITMASK, mfma);
+  stats->sweep1_tests = L.prune ? (int64_t)hst.tests
+                                 : sweep_tests(n, L.n_pad, d, L.adjacency == DBSCAN_ADJ_BITMASK,
+                                               mfma);
+  stats->pruned = L.prune ? 1 : 0;
   stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
   return stats->status;
 }

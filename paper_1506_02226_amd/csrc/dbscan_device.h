@@ -37,6 +37,7 @@ struct DevState {
   float thr[2];                    // matrix-core filter thresholds (in, out)
   unsigned long long reserved[2];
   unsigned int box_lo[4], box_hi[4];  // bounding box of the input (order-preserving bits)
+  unsigned long long tests;           // pair tests made by a pruned sweep
 };
 
 constexpr int kNoNeighbour = 0x7fffffff;
@@ -143,6 +144,65 @@ __device__ __forceinline__ float min_of(const float (&v)[G]) {
     const float c = __builtin_fminf(__builtin_fminf(v[6], v[7]), a);
     return __builtin_fminf(b, c);
   }
+}
+
+// ------------------------------------------------------------ tile pruning
+// Squared gap between two boxes (per-coordinate lo / hi) evaluated like a
+// pair's squared distance: the corners are float32 coordinates of the input,
+// so the band's guarantee holds for them -- gap2 > hi means the float64
+// value of the corners' squared distance exceeds eps^2 -- and every real pair
+// from the two boxes has per-coordinate differences at least the gaps, whose
+// rounded squares and sums are then no smaller (rounding is monotone): no
+// pair of the two boxes is a neighbour.  An empty box (lo = +inf, hi = -inf)
+// gives an infinite gap.
+template <int D>
+__device__ __forceinline__ float box_gap2(const float (&alo)[D], const float (&ahi)[D],
+                                          const float (&blo)[D], const float (&bhi)[D]) {
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    const float g = __builtin_fmaxf(__builtin_fmaxf(blo[k] - ahi[k], alo[k] - bhi[k]), 0.0f);
+    s = __builtin_fmaf(g, g, s);
+  }
+  return s;
+}
+
+// Lane l takes the box of 64-point block b0 + l from the per-block boxes
+// `box` ([2k][nb] lo, [2k+1][nb] hi); lanes past b1 take an empty box.
+template <int D>
+__device__ __forceinline__ void lane_box(const float *__restrict__ box, int nb, int b0, int b1,
+                                         float (&lo)[D], float (&hi)[D]) {
+  const int b = b0 + lane_id();
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    lo[k] = b < b1 ? box[(size_t)(2 * k) * nb + b] : __builtin_inff();
+    hi[k] = b < b1 ? box[(size_t)(2 * k + 1) * nb + b] : -__builtin_inff();
+  }
+}
+
+// Union of the lanes' boxes (the same value in every lane).
+template <int D>
+__device__ __forceinline__ void wave_box(const float (&lo)[D], const float (&hi)[D],
+                                         float (&ulo)[D], float (&uhi)[D]) {
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    float l = lo[k], h = hi[k];
+    for (int off = 32; off > 0; off >>= 1) {
+      l = __builtin_fminf(l, __shfl_xor(l, off));
+      h = __builtin_fmaxf(h, __shfl_xor(h, off));
+    }
+    ulo[k] = l;
+    uhi[k] = h;
+  }
+}
+
+// Box of the 64-point blocks [b0, b1) (b1 - b0 <= 64), in every lane.
+template <int D>
+__device__ __forceinline__ void span_box(const float *__restrict__ box, int nb, int b0, int b1,
+                                         float (&lo)[D], float (&hi)[D]) {
+  float l[D], h[D];
+  lane_box<D>(box, nb, b0, b1, l, h);
+  wave_box<D>(l, h, lo, hi);
 }
 
 // Re-decide the lanes in `band` in float64; returns the exact in-mask.

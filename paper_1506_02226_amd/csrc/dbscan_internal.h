@@ -47,6 +47,7 @@ struct SweepScalars {
   long long edge_cap;  // capacity of the pair list (entries)
   int flags;           // kOnlyOnOverflow / kOnlyOnFilterFail
   int rgroup;          // rows per block of the triangular sweeps (multiple of 64)
+  const float *box;    // per-64-point-block boxes (tile pruning), [2k][n_pad/64] lo / hi
 };
 
 constexpr int kOnlyOnOverflow = 1;    // run only if the pair list overflowed
@@ -79,6 +80,7 @@ hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], 
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
                      int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s);
 hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s);
+hipError_t run_block_boxes(const float *soa, int n_pad, int d, float *box, hipStream_t s);
 hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);

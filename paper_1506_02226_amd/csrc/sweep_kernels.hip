@@ -34,7 +34,7 @@ __device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevStat
 // Triangular form (each unordered pair tested once); LDS column tallies.
 constexpr int kTriMaxChunk = 4096;
 
-template <int D, int R, bool EMIT>
+template <int D, int R, bool EMIT, bool PRUNE>
 __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa,
                                                    int *__restrict__ counts,
                                                    int2 *__restrict__ pairs,
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa
   __shared__ int colcnt[kTriMaxChunk];
   __shared__ unsigned long long xfer[5];
   if (skip_sweep(sc, st)) return;
-  count_tri_body<D, R, EMIT>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
+  count_tri_body<D, R, EMIT, PRUNE>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
 }
 
 // --------------------------------------- merge repeated on the fly, d <= 4
@@ -568,13 +568,19 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
     }
     return hipGetLastError();
   }
-#define DBK_COUNT(D)                                                                          \
+#define DBK_COUNT_P(D, P)                                                                     \
   if (emit_pairs)                                                                             \
-    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true>), tgrid, block, 0, s, b.soa,        \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true, P>), tgrid, block, 0, s, b.soa,     \
                        b.counts, b.pairs, b.st, sc);                                          \
   else                                                                                        \
-    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, false>), tgrid, block, 0, s, b.soa,       \
-                       b.counts, b.pairs, b.st, sc);                                          \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, false, P>), tgrid, block, 0, s, b.soa,    \
+                       b.counts, b.pairs, b.st, sc);
+#define DBK_COUNT(D)                                                                          \
+  if (sc.box) {                                                                               \
+    DBK_COUNT_P(D, true)                                                                      \
+  } else {                                                                                    \
+    DBK_COUNT_P(D, false)                                                                     \
+  }                                                                                           \
   break;
   switch (sc.d) {
     case 1: DBK_COUNT(1)
@@ -584,6 +590,7 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
     default: return hipErrorInvalidValue;
   }
 #undef DBK_COUNT
+#undef DBK_COUNT_P
   return hipGetLastError();
 }
 

@@ -141,8 +141,25 @@ def test_order_option_layout():
     o.order = 9
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
     o.order = 0
-    o.reserved = 1
+    o.prune = 2
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL
+
+
+def test_prune_option():
+    """Tile pruning: float32 forms with d <= 4 only; it adds the per-64-point
+    block boxes (2 d floats per block) to the workspace."""
+    L = _lib.load()
+    out = ctypes.c_uint64()
+    sizes = {}
+    for prune in (False, True):
+        o = _lib.make_opts("onthefly", "fp32", prune=prune)
+        assert L.dbscan_workspace_size(100_000, 3, ctypes.byref(o), ctypes.byref(out)) == 0
+        sizes[prune] = out.value
+    assert sizes[True] - sizes[False] == (2 * 3 * (100_096 // 64) * 4 + 255) // 256 * 256
+    for d, prec in ((5, "fp32"), (16, "fp16"), (2, "fp16")):
+        o = _lib.make_opts("onthefly", prec, prune=True)
+        assert L.dbscan_workspace_size(1000, d, ctypes.byref(o), ctypes.byref(out)) == \
+            _lib.DBSCAN_E_UNSUPPORTED
 
 
 def _band(eps2, d):
