@@ -4,6 +4,7 @@
 // Section IV-C read from it.
 #include "dbscan_device.h"
 #include "dbscan_internal.h"
+#include "bodies_sweep.h"
 
 namespace dbk {
 
@@ -48,18 +49,17 @@ constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 // tests the 64 column boxes of its chunk at once, one per lane, and visits
 // only the blocks within reach); the tests actually made go to st->tests.
 template <int D, bool PRUNE>
-__global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
-                                                 uint32_t *__restrict__ adj,
-                                                 uint8_t *__restrict__ tflag,
-                                                 int *__restrict__ counts,
-                                                 DevState *__restrict__ st, SweepScalars sc) {
+__device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
+                                             uint32_t *__restrict__ adj,
+                                             uint8_t *__restrict__ tflag,
+                                             int *__restrict__ counts, DevState *__restrict__ st,
+                                             const SweepScalars &sc, int bid, int *colcnt,
+                                             uint8_t (*tiles)[kBitmaskMaxChunk / 64]) {
   constexpr int R = 32, G = 8;
-  __shared__ int colcnt[kBitmaskMaxChunk];
-  __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];  // non-empty flags
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
-  const int chunk = blockIdx.x % sc.nchunks;
-  const int g0 = (blockIdx.x / sc.nchunks) * sc.rgroup;
+  const int chunk = bid % sc.nchunks;
+  const int g0 = (bid / sc.nchunks) * sc.rgroup;
   const int c0 = chunk * sc.chunk;
   const int c1 = min(c0 + sc.chunk, sc.n_pad);
   if (g0 >= sc.n_pad || c1 <= g0) return;  // block-uniform
@@ -204,6 +204,33 @@ __global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
     const int q = g0 / 32 + rr, cb = c0 + 64 * cc;
     if (cb >= ((32 * q) & ~63)) tflag[(size_t)(cb >> 6) * nq + q] = tiles[rr][cc];
   }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
+                                                 uint32_t *__restrict__ adj,
+                                                 uint8_t *__restrict__ tflag,
+                                                 int *__restrict__ counts,
+                                                 DevState *__restrict__ st, SweepScalars sc) {
+  __shared__ int colcnt[kBitmaskMaxChunk];
+  __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];  // non-empty flags
+  bitmask_body<D, false>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
+}
+
+// Pruned form: a persistent grid over the blocks that survive the coarse
+// box test (for_near_blocks), the flags cleared beforehand.
+template <int D>
+__global__ __launch_bounds__(256) void k_bitmask_pruned(const float *__restrict__ soa,
+                                                        uint32_t *__restrict__ adj,
+                                                        uint8_t *__restrict__ tflag,
+                                                        int *__restrict__ counts,
+                                                        DevState *__restrict__ st,
+                                                        SweepScalars sc) {
+  __shared__ int colcnt[kBitmaskMaxChunk];
+  __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];
+  for_near_blocks<D>(sc, sc.n_pad, [&](int bid) {
+    bitmask_body<D, true>(soa, adj, tflag, counts, st, sc, bid, colcnt, tiles);
+  });
 }
 
 // --------------------------------------------------- merge from the bitmask
@@ -418,6 +445,8 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
   const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
   const dim3 grid(groups * sc.nchunks), block(256);
   if (sc.box) {
+    hipError_t e = run_coarse_boxes(sc, s);
+    if (e != hipSuccess) return e;
     // n_pad is a multiple of 256, so the flags are whole 16-byte pieces
     const long long n16 = (long long)(sc.n_pad / 64) * (sc.n_pad / 32) / 16;
     hipLaunchKernelGGL(k_clear_flags, dim3(n16 < 4096 * 256 ? (unsigned)((n16 + 255) / 256) : 4096),
@@ -426,10 +455,10 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 #define DBK_BITMASK(D)                                                                        \
   case D:                                                                                     \
     if (sc.box)                                                                               \
-      hipLaunchKernelGGL((k_bitmask<D, true>), grid, block, 0, s, b.soa, (uint32_t *)b.adjT,  \
-                         b.tflag, b.counts, b.st, sc);                                        \
+      hipLaunchKernelGGL((k_bitmask_pruned<D>), dim3(pruned_grid(grid.x)), block, 0, s, b.soa, \
+                         (uint32_t *)b.adjT, b.tflag, b.counts, b.st, sc);                    \
     else                                                                                      \
-      hipLaunchKernelGGL((k_bitmask<D, false>), grid, block, 0, s, b.soa, (uint32_t *)b.adjT, \
+      hipLaunchKernelGGL((k_bitmask<D>), grid, block, 0, s, b.soa, (uint32_t *)b.adjT,        \
                          b.tflag, b.counts, b.st, sc);                                        \
     break;
   switch (sc.d) {

@@ -359,7 +359,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
     __syncthreads();
     bcur = bnext;
   }
-  wq_flush_block(qp, pairs, sc.pair_cap, &st->edges, &st->status, kStatusEdgeOverflow, lds.xfer);
+  wq_flush_pairs(qp, pairs, sc.pair_cap, st, lds.xfer);
   wq_flush_block(qb, band, sc.band_cap, &st->band_list, &st->status, kStatusBandOverflow, lds.xfer);
   // row-side counts (wq_flush_block ends with a barrier)
   for (int k = tid; k < sc.chunk * 16; k += 256) {

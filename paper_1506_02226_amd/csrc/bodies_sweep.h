@@ -16,6 +16,51 @@ __device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const f
   return recheck_band<D>(m & ~in, in, a, b, eps2, st);
 }
 
+// ------------------------------------------------------ pruned launches
+// Persistent form of the triangular sweeps with tile pruning: work-group b
+// of the grid takes the (row group, column chunk) blocks b, b + G, b + 2G,
+// ... (G = grid size), 64 at a time -- each lane tests one block's row-group
+// box against its chunk's box (coarse boxes at sc.box + 2 d nb and + 4 d nb)
+// -- and runs body(bid) for the blocks within reach only, one after another.
+// Every wave computes the same mask, so the loop is block-uniform and the
+// body may synchronise the block.
+template <int D, typename F>
+__device__ __forceinline__ void for_near_blocks(const SweepScalars &sc, int rows_end, F &&body) {
+  const int nb = sc.n_pad / 64;
+  const float *gbox = sc.box + 2 * D * nb;  // [2k][row group]
+  const float *kbox = sc.box + 4 * D * nb;  // [2k][chunk]
+  const long long groups = (rows_end + sc.rgroup - 1) / sc.rgroup;
+  const long long total = groups * sc.nchunks;
+  const long long G = gridDim.x;
+  for (long long it = 0; (long long)blockIdx.x + it * 64 * G < total; ++it) {
+    const long long id = (long long)blockIdx.x + (it * 64 + lane_id()) * G;
+    bool near = false;
+    if (id < total) {
+      const int rg = (int)(id / sc.nchunks), ch = (int)(id - (long long)rg * sc.nchunks);
+      const int g0 = rg * sc.rgroup;
+      const int c1 = min(ch * sc.chunk + sc.chunk, sc.n_pad);
+      if (c1 > g0) {  // the triangle: some column at or after the block's rows
+        float alo[D], ahi[D], blo[D], bhi[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          alo[k] = gbox[(size_t)(2 * k) * nb + rg];
+          ahi[k] = gbox[(size_t)(2 * k + 1) * nb + rg];
+          blo[k] = kbox[(size_t)(2 * k) * nb + ch];
+          bhi[k] = kbox[(size_t)(2 * k + 1) * nb + ch];
+        }
+        near = box_gap2<D>(alo, ahi, blo, bhi) <= sc.hi;
+      }
+    }
+    uint64_t m = __ballot(near);
+    while (m != 0ull) {
+      const int b = __builtin_ctzll(m);
+      m &= m - 1ull;
+      body((int)((long long)blockIdx.x + (it * 64 + b) * G));
+      __syncthreads();  // the body's LDS is reused by the next block
+    }
+  }
+}
+
 // ------------------------------- step 1 + counts, d <= 4, one test per pair
 // A block owns sc.rgroup rows and
 // the sc.chunk columns of one chunk, and an R-row block of a wave only visits
@@ -176,7 +221,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
   }
   if (PRUNE && lane == 0 && tested) atomicAdd(&st->tests, tested);
-  if (EMIT) wq_flush_block(qu, pairs, sc.edge_cap, &st->edges, &st->status, kStatusEdgeOverflow, xfer);
+  if (EMIT) wq_flush_pairs(qu, pairs, sc.edge_cap, st, xfer);
   __syncthreads();
   for (int t = threadIdx.x; t < c1 - c0; t += 256) {
     const int v = colcnt[t];

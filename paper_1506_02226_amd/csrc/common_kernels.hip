@@ -9,8 +9,10 @@
 namespace dbk {
 
 // ------------------------------------------------------------------ staging
-__global__ void k_reset_state(DevState *st) {
+__global__ void k_reset_state(DevState *st, unsigned pair_segs) {
+  if (threadIdx.x < kPairSegments) st->edge_seg[threadIdx.x][0] = 0;
   if (threadIdx.x == 0) {
+    st->pair_segs = pair_segs;
     st->status = 0;
     st->noncore = 0;
     st->band_pairs = 0;
@@ -74,13 +76,18 @@ __global__ __launch_bounds__(256) void k_merge_list(const int2 *__restrict__ pai
                                                     long long cap, const int *__restrict__ okey) {
   const unsigned status = __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (status & kStatusEdgeOverflow) return;
-  unsigned long long total =
-      __hip_atomic_load(&st->edges, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (total > (unsigned long long)cap) total = (unsigned long long)cap;
-  const unsigned long long per = (total + gridDim.x - 1) / gridDim.x;
-  const unsigned long long b = (unsigned long long)blockIdx.x * per;
+  // segment of this block (the list is one segment when pair_segs <= 1)
+  const unsigned S = st->pair_segs > 1u ? st->pair_segs : 1u;
+  const unsigned sgm = blockIdx.x % S, part = blockIdx.x / S, parts = gridDim.x / S;
+  if (part >= parts) return;
+  const unsigned long long seg_cap = (unsigned long long)cap / S;
+  unsigned long long total = __hip_atomic_load(S > 1u ? &st->edge_seg[sgm][0] : &st->edges,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (total > seg_cap) total = seg_cap;
+  const unsigned long long per = (total + parts - 1) / parts;
+  const unsigned long long b = (unsigned long long)part * per;
   const unsigned long long e = b + per < total ? b + per : total;
-  merge_pairs_range(pairs, corebits, parent, jstar, b, e, okey);
+  merge_pairs_range(pairs + sgm * seg_cap, corebits, parent, jstar, b, e, okey);
 }
 
 // ------------------------------------------------------------------ labels
@@ -97,19 +104,21 @@ __global__ void k_labels(int n, const uint32_t *__restrict__ corebits,
 }
 
 // ----------------------------------------------------- filter fallback
-// When the matrix-core filter gave up (inputs out of its range, or too many
-// undecided pairs), clear the counts for the float32 sweep that redoes step 1
-// and mark the pair list as incomplete so that step 3 repeats the tests.
-// When the matrix-core filter gave up: clear the counts, stage the float32
-// coordinates for the sweeps that redo step 1 (the filtered path does not
-// need them), and mark the pair list incomplete so step 3 repeats the tests.
+// The matrix-core path stages no float32 coordinates of its own.  When its
+// filter gave up (inputs out of its range, or too many undecided pairs): clear
+// the counts, stage the coordinates for the float32 sweep that redoes step 1,
+// and mark the pair list incomplete so that step 3 repeats the tests.  When
+// only the pair list ran out of room: stage the coordinates for the sweeps of
+// step 3 that repeat the tests.
 __global__ void k_filter_fallback(const float *__restrict__ pts, const int *__restrict__ perm,
                                   int n, int d, int n_pad, int d_pad, float *__restrict__ soa,
                                   int *__restrict__ counts, DevState *st) {
   const unsigned status =
       __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!(status & (kStatusRange | kStatusBandOverflow))) return;
+  const bool filter_failed = (status & (kStatusRange | kStatusBandOverflow)) != 0u;
+  if (!filter_failed && !(status & kStatusEdgeOverflow)) return;
   stage_soa_body(pts, n, d, n_pad, d_pad, soa, st, blockIdx.x, perm);
+  if (!filter_failed) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) counts[i] = 0;
   if (i == 0) atomicOr(&st->status, kStatusEdgeOverflow);
@@ -144,8 +153,12 @@ hipError_t run_block_boxes(const float *soa, int n_pad, int d, float *box, hipSt
   return hipGetLastError();
 }
 
-hipError_t run_reset(DevState *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st);
+hipError_t run_reset(DevState *st, long long pair_cap, hipStream_t s) {
+  // segments of at least 2^18 entries, so a small list is not split into
+  // pieces that one block could fill
+  long long segs = pair_cap >> 18;
+  segs = segs < 1 ? 1 : (segs > kPairSegments ? kPairSegments : segs);
+  hipLaunchKernelGGL(k_reset_state, dim3(1), dim3(64), 0, s, st, (unsigned)segs);
   return hipGetLastError();
 }
 

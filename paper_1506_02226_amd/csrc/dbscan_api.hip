@@ -136,7 +136,8 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     L->off_counts = take((uint64_t)L->n_pad * 4);
     L->off_rootmin = take((uint64_t)L->n_pad * 4);
   }
-  if (L->prune) L->off_box = take((uint64_t)2 * d * (L->n_pad / 64) * 4);
+  // boxes of the 64-point blocks, then of the row groups and of the chunks
+  if (L->prune) L->off_box = take((uint64_t)3 * 2 * d * (L->n_pad / 64) * 4);
   L->total = off;
   return DBSCAN_OK;
 }
@@ -359,7 +360,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     if (e == hipSuccess && r != hipSuccess) e = r;
   };
 
-  step(dbk::run_reset(st, s));
+  step(dbk::run_reset(st, L.edge_cap, s));
   // spatial order: the permutation first, then the staging gathers through it
   // and the kernels count into a staged-order array (scattered back by the
   // core-flag pass)
@@ -529,7 +530,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   stats->ms_total = t03;
   stats->thr_lo = lo;
   stats->thr_hi = hi;
-  stats->pairs_listed = (int64_t)hst.edges;
+  uint64_t listed = hst.edges;
+  for (int g = 0; g < dbk::kPairSegments; ++g) listed += hst.edge_seg[g][0];
+  stats->pairs_listed = (int64_t)listed;
   stats->pair_overflow = (hst.status & dbk::kStatusEdgeOverflow) ? 1 : 0;
   stats->filter_fallback = (hst.status & (dbk::kStatusRange | dbk::kStatusBandOverflow)) ? 1 : 0;
   stats->thr_lo = mfma ? hst.thr[0] : lo;

@@ -25,7 +25,7 @@ constexpr unsigned kStatusRange = 8u;          // inputs outside the low-precisi
 constexpr int kPrecBf16 = 2;  // values of dbscan_opts.precision
 constexpr int kPrecFp16 = 3;
 
-// Per-call device state (first 256 bytes of the workspace).
+// Per-call device state (first section of the workspace).
 struct DevState {
   unsigned int status;             // kStatus* bits
   unsigned int noncore;            // compaction cursor for non-core rows
@@ -38,7 +38,16 @@ struct DevState {
   unsigned long long reserved[2];
   unsigned int box_lo[4], box_hi[4];  // bounding box of the input (order-preserving bits)
   unsigned long long tests;           // pair tests made by a pruned sweep
+  // Pair list in segments (0 or 1: one list at `edges`): segment s holds
+  // entries [s * cap / pair_segs, ...) and counts its appends in
+  // edge_seg[s][0], so the appends of many blocks spread over several
+  // counters, each on a 128-byte line of its own.
+  unsigned int pair_segs;
+  unsigned int pad0;
+  unsigned long long edge_seg[32][16];
 };
+
+constexpr int kPairSegments = 32;  // segments of the standalone pair list
 
 constexpr int kNoNeighbour = 0x7fffffff;
 
@@ -391,10 +400,35 @@ __device__ __forceinline__ void wq_flush_block(WaveQueue &q, int2 *list, long lo
   __syncthreads();  // xfer is reused by the next flush
 }
 
+// The pair-list segment of this work-group: its first entry, capacity and
+// append counter.
+struct PairSegment {
+  int2 *list;
+  long long cap;
+  unsigned long long *cursor;
+};
+
+__device__ __forceinline__ PairSegment pair_segment(int2 *list, long long cap, DevState *st) {
+  const unsigned S = st->pair_segs;
+  if (S <= 1u) return PairSegment{list, cap, &st->edges};
+  const unsigned sgm = blockIdx.x % S;
+  const long long seg_cap = cap / S;
+  return PairSegment{list + sgm * seg_cap, seg_cap, &st->edge_seg[sgm][0]};
+}
+
 // Neighbour pairs (i, j), j < i, for the merge.
 __device__ __forceinline__ void wq_drain_list(WaveQueue &q, int2 *list, long long cap,
                                               DevState *st, bool all) {
-  wq_drain_to(q, list, cap, &st->edges, &st->status, kStatusEdgeOverflow, all);
+  if (q.count < q.limit && !(all && q.count > 0)) return;
+  const PairSegment g = pair_segment(list, cap, st);
+  wq_drain_to(q, g.list, g.cap, g.cursor, &st->status, kStatusEdgeOverflow, all);
+}
+
+// End of a block for a pair-list queue (wq_flush_block on this block's segment).
+__device__ __forceinline__ void wq_flush_pairs(WaveQueue &q, int2 *list, long long cap,
+                                               DevState *st, unsigned long long *xfer) {
+  const PairSegment g = pair_segment(list, cap, st);
+  wq_flush_block(q, g.list, g.cap, g.cursor, &st->status, kStatusEdgeOverflow, xfer);
 }
 
 // Pairs the matrix-core filter could not decide.

@@ -47,8 +47,13 @@ struct SweepScalars {
   long long edge_cap;  // capacity of the pair list (entries)
   int flags;           // kOnlyOnOverflow / kOnlyOnFilterFail
   int rgroup;          // rows per block of the triangular sweeps (multiple of 64)
-  const float *box;    // per-64-point-block boxes (tile pruning), [2k][n_pad/64] lo / hi
+  float *box;          // tile pruning: boxes of the 64-point blocks, [2k][n_pad/64] lo / hi,
+                       // then the same for row groups and for column chunks
 };
+
+// Tile pruning: launch helpers of the persistent sweeps.
+hipError_t run_coarse_boxes(const SweepScalars &sc, hipStream_t s);
+unsigned pruned_grid(unsigned full_grid);
 
 constexpr int kOnlyOnOverflow = 1;    // run only if the pair list overflowed
 constexpr int kOnlyOnFilterFail = 2;  // run only if the matrix-core filter gave up
@@ -72,7 +77,7 @@ __host__ __device__ inline long long mfma_items_before(int g, int nchunks, int k
 int rows_per_wave(int d);
 int coord_chunk(int d);
 
-hipError_t run_reset(DevState *st, hipStream_t s);
+hipError_t run_reset(DevState *st, long long pair_cap, hipStream_t s);
 long long order_hist_entries(long long n);
 int order_max_d();
 hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], int *vals[2],

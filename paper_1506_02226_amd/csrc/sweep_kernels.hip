@@ -46,6 +46,63 @@ __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa
   count_tri_body<D, R, EMIT, PRUNE>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
 }
 
+// Pruned form: a persistent grid over the blocks within reach.
+template <int D, int R, bool EMIT>
+__global__ __launch_bounds__(256) void k_count_tri_pruned(const float *__restrict__ soa,
+                                                          int *__restrict__ counts,
+                                                          int2 *__restrict__ pairs,
+                                                          DevState *__restrict__ st,
+                                                          SweepScalars sc) {
+  __shared__ int2 qbuf[4][kListQueue];
+  __shared__ int colcnt[kTriMaxChunk];
+  __shared__ unsigned long long xfer[5];
+  if (skip_sweep(sc, st)) return;
+  for_near_blocks<D>(sc, sc.n, [&](int bid) {
+    count_tri_body<D, R, EMIT, true>(soa, counts, pairs, st, sc, bid, qbuf, colcnt, xfer);
+  });
+}
+
+// Boxes of the row groups and of the column chunks of a pruned sweep, each
+// the union of its 64-point block boxes (one wave per box; at most 64
+// blocks each).
+__global__ __launch_bounds__(256) void k_coarse_boxes(float *__restrict__ box, int n_pad, int d,
+                                                      int rgroup, int groups, int chunk,
+                                                      int nchunks) {
+  const int nb = n_pad / 64;
+  const int wv = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (wv >= groups + nchunks) return;
+  const bool is_group = wv < groups;
+  const int idx = is_group ? wv : wv - groups;
+  const int span = is_group ? rgroup : chunk;
+  const int b0 = idx * span / 64, b1 = min((idx + 1) * span, n_pad) / 64;
+  float *out = box + (is_group ? 2 : 4) * d * nb;
+  const int b = b0 + lane_id();
+  for (int k = 0; k < d; ++k) {
+    float l = b < b1 ? box[(size_t)(2 * k) * nb + b] : __builtin_inff();
+    float h = b < b1 ? box[(size_t)(2 * k + 1) * nb + b] : -__builtin_inff();
+    for (int off = 32; off > 0; off >>= 1) {
+      l = __builtin_fminf(l, __shfl_xor(l, off));
+      h = __builtin_fmaxf(h, __shfl_xor(h, off));
+    }
+    if (lane_id() == 0) {
+      out[(size_t)(2 * k) * nb + idx] = l;
+      out[(size_t)(2 * k + 1) * nb + idx] = h;
+    }
+  }
+}
+
+hipError_t run_coarse_boxes(const SweepScalars &sc, hipStream_t s) {
+  const int nb = sc.n_pad / 64;
+  const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;
+  if (sc.rgroup > 64 * 64 || sc.chunk > 64 * 64 || groups > nb || sc.nchunks > nb)
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coarse_boxes, dim3((groups + sc.nchunks + 3) / 4), dim3(256), 0, s, sc.box,
+                     sc.n_pad, sc.d, sc.rgroup, groups, sc.chunk, sc.nchunks);
+  return hipGetLastError();
+}
+
+unsigned pruned_grid(unsigned full_grid) { return full_grid < 4096 ? full_grid : 4096; }
+
 // --------------------------------------- merge repeated on the fly, d <= 4
 // Core rows i queue their core neighbours j < i; the queue is drained into
 // the union-find 64 pairs at a time.
@@ -319,7 +376,7 @@ __global__ __launch_bounds__(256) void k_count_tri_lds(const float *__restrict__
     const int row = row0 + lane;
     if (lane < R && row < sc.n && mine != 0) atomicAdd(counts + row, mine);
   }
-  if (EMIT) wq_flush_block(qu, pairs, sc.edge_cap, &st->edges, &st->status, kStatusEdgeOverflow, xfer);
+  if (EMIT) wq_flush_pairs(qu, pairs, sc.edge_cap, st, xfer);
   __syncthreads();
   for (int t = threadIdx.x; t < c1 - c0; t += 256) {
     const int v = colcnt[t];
@@ -547,6 +604,11 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
   if (sc.chunk % 64 != 0 || sc.chunk > kTriMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0)
     return hipErrorInvalidValue;
   const dim3 tgrid(((sc.n + sc.rgroup - 1) / sc.rgroup) * sc.nchunks);
+  const dim3 pgrid(pruned_grid(tgrid.x));
+  if (sc.box && sc.d <= 4) {
+    hipError_t e = run_coarse_boxes(sc, s);
+    if (e != hipSuccess) return e;
+  }
   if (sc.d > 4) {
     const size_t lds = (size_t)4 * kRowsLds * sc.d_pad * sizeof(float);
     switch (coord_chunk(sc.d)) {
@@ -568,18 +630,20 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
     }
     return hipGetLastError();
   }
-#define DBK_COUNT_P(D, P)                                                                     \
-  if (emit_pairs)                                                                             \
-    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true, P>), tgrid, block, 0, s, b.soa,     \
-                       b.counts, b.pairs, b.st, sc);                                          \
-  else                                                                                        \
-    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, false, P>), tgrid, block, 0, s, b.soa,    \
-                       b.counts, b.pairs, b.st, sc);
 #define DBK_COUNT(D)                                                                          \
   if (sc.box) {                                                                               \
-    DBK_COUNT_P(D, true)                                                                      \
+    if (emit_pairs)                                                                           \
+      hipLaunchKernelGGL((k_count_tri_pruned<D, kRowsSmall, true>), pgrid, block, 0, s,       \
+                         b.soa, b.counts, b.pairs, b.st, sc);                                 \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_count_tri_pruned<D, kRowsSmall, false>), pgrid, block, 0, s,      \
+                         b.soa, b.counts, b.pairs, b.st, sc);                                 \
+  } else if (emit_pairs) {                                                                    \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, true, false>), tgrid, block, 0, s, b.soa,  \
+                       b.counts, b.pairs, b.st, sc);                                          \
   } else {                                                                                    \
-    DBK_COUNT_P(D, false)                                                                     \
+    hipLaunchKernelGGL((k_count_tri<D, kRowsSmall, false, false>), tgrid, block, 0, s, b.soa, \
+                       b.counts, b.pairs, b.st, sc);                                          \
   }                                                                                           \
   break;
   switch (sc.d) {
@@ -590,7 +654,6 @@ hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, 
     default: return hipErrorInvalidValue;
   }
 #undef DBK_COUNT
-#undef DBK_COUNT_P
   return hipGetLastError();
 }
 

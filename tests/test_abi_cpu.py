@@ -146,8 +146,9 @@ def test_order_option_layout():
 
 
 def test_prune_option():
-    """Tile pruning: float32 forms with d <= 4 only; it adds the per-64-point
-    block boxes (2 d floats per block) to the workspace."""
+    """Tile pruning: float32 forms with d <= 4 only; it adds the boxes of the
+    64-point blocks, row groups and column chunks (3 x 2 d floats per block)
+    to the workspace."""
     L = _lib.load()
     out = ctypes.c_uint64()
     sizes = {}
@@ -155,7 +156,7 @@ def test_prune_option():
         o = _lib.make_opts("onthefly", "fp32", prune=prune)
         assert L.dbscan_workspace_size(100_000, 3, ctypes.byref(o), ctypes.byref(out)) == 0
         sizes[prune] = out.value
-    assert sizes[True] - sizes[False] == (2 * 3 * (100_096 // 64) * 4 + 255) // 256 * 256
+    assert sizes[True] - sizes[False] == (3 * 2 * 3 * (100_096 // 64) * 4 + 255) // 256 * 256
     for d, prec in ((5, "fp32"), (16, "fp16"), (2, "fp16")):
         o = _lib.make_opts("onthefly", prec, prune=True)
         assert L.dbscan_workspace_size(1000, d, ctypes.byref(o), ctypes.byref(out)) == \

@@ -279,6 +279,23 @@ def test_mfma_integer_ties(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("cap", [1, 500])
+def test_mfma_pair_overflow(prec, cap):
+    """Matrix-core filter that decides every pair, but a pair list too small
+    for the merge: step 3 repeats the tests in float32 from coordinates the
+    matrix-core path stages only for this case."""
+    w = wl.by_name("mix64d_300k_q50", 0, 4000)
+    ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
+    for order in ("input", "spatial"):
+        gpu = run(w.points, w.eps, w.minpts, adjacency="onthefly", precision=prec, order=order,
+                  pair_capacity=cap, stats=True)
+        st = gpu[3]
+        assert st["precision_used"] == prec and st["filter_fallback"] == 0
+        assert st["pair_overflow"] == 1
+        assert_same(gpu, ref, f"{prec} cap={cap} {order}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_mfma_band_overflow_and_range_fallback(prec):
     w = wl.mix64d_300k(0, n=3000, eps_rule="q50")
     ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
