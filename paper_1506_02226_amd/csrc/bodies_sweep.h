@@ -79,13 +79,13 @@ __device__ __forceinline__ void for_near_blocks(const SweepScalars &sc, int rows
 // rows' box (all 64 blocks of the chunk tested at once, one per lane).
 // Skipped pairs are provably not neighbours; the tests actually made go to
 // st->tests.
-template <int D, int R, bool EMIT, bool PRUNE = false>
+template <int D, int R, bool EMIT, bool PRUNE = false, int QN = kListQueue>
 __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
                                                int *__restrict__ counts,
                                                int2 *__restrict__ pairs,
                                                DevState *__restrict__ st,
                                                const SweepScalars &sc, int bid,
-                                               int2 (*qbuf)[kListQueue], int *colcnt,
+                                               int2 (*qbuf)[QN], int *colcnt,
                                                unsigned long long *xfer) {
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
@@ -109,7 +109,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
   }
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
   __syncthreads();
-  WaveQueue qu{qbuf[w], 0, kListDrain};
+  WaveQueue qu{qbuf[w], 0, QN - 64};  // appended once QN - 64 pairs are queued
   unsigned long long tested = 0;  // PRUNE: pair tests made by this wave
   for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
     const int diag = row0 & ~63;

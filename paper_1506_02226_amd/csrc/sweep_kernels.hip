@@ -46,19 +46,24 @@ __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa
   count_tri_body<D, R, EMIT, PRUNE>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
 }
 
-// Pruned form: a persistent grid over the blocks within reach.
+// Pruned form: a persistent grid over the blocks within reach.  Its tiles
+// are mostly ones with neighbours, so the pairs come fast: the wave queues
+// are four times longer, so that appends to the list are rarer.
+constexpr int kPrunedQueue = 4 * kListDrain + 64;
+
 template <int D, int R, bool EMIT>
 __global__ __launch_bounds__(256) void k_count_tri_pruned(const float *__restrict__ soa,
                                                           int *__restrict__ counts,
                                                           int2 *__restrict__ pairs,
                                                           DevState *__restrict__ st,
                                                           SweepScalars sc) {
-  __shared__ int2 qbuf[4][kListQueue];
+  __shared__ int2 qbuf[4][kPrunedQueue];
   __shared__ int colcnt[kTriMaxChunk];
   __shared__ unsigned long long xfer[5];
   if (skip_sweep(sc, st)) return;
   for_near_blocks<D>(sc, sc.n, [&](int bid) {
-    count_tri_body<D, R, EMIT, true>(soa, counts, pairs, st, sc, bid, qbuf, colcnt, xfer);
+    count_tri_body<D, R, EMIT, true, kPrunedQueue>(soa, counts, pairs, st, sc, bid, qbuf, colcnt,
+                                                   xfer);
   });
 }
 
