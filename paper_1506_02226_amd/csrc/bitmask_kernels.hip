@@ -11,15 +11,15 @@ namespace dbk {
 // ----------------------------------------------------- bitmask pass (d <= 4)
 // One wave takes 32 rows at a time (the "goal points" of Section IV-A.3,
 // wave-uniform values held in vector registers so that the subtractions issue
-// at the full rate) and the 64 lanes hold 64 columns.  Per row, one compare
-// gives the 64-bit ballot of the row's neighbours among the columns; only
-// when a ballot is not empty -- rare at these densities, and tested once per
-// group of 4 rows -- does its popcount go to the row's count (scalar unit)
-// and the lane set bit r of its 32-bit word.  After the 32 rows, lane j holds
-// the pairs (rows
-// row0..row0+31, column j); by symmetry that is row j's word for the columns
-// row0..row0+31, stored at adj[row0/32][j] -- a coalesced 256-byte store per
-// wave.  Bit b of adj[q][i] is the pair (i, 32q+b).  Padded rows and columns
+// at the full rate) and the 64 lanes hold 64 columns.  Per group of 8 rows
+// one compare of the distances' minimum tells whether any row has a
+// neighbour among the columns; only then -- rare at these densities -- does
+// each row's ballot give its popcount to the row's count (scalar unit) and
+// the lane set bit r of its 32-bit word.  (64 rows per wave at d = 2 take 188
+// vector registers and ran a third slower.)  After the 32 rows, lane j holds
+// the pairs (rows row0..row0+31, column j); by symmetry that is row j's word
+// for the columns row0..row0+31, stored at adj[row0/32][j] -- a coalesced
+// 256-byte store per wave.  Bit b of adj[q][i] is the pair (i, 32q+b).  Padded rows and columns
 // (index >= n) are NaN, so their bits are zero.  Each 32 x 64 tile also gets
 // a flag byte, tflag[j/64][row0/32], telling whether any of its bits is set
 // (the merge reads only flagged tiles); the flags are gathered in LDS and
