@@ -35,7 +35,7 @@ struct Order {
 // Bits per coordinate of the spatial-order key for d <= 4 (at most 32 in all;
 // larger d use a pivot index, one radix pass).
 __host__ __device__ inline int order_bits_per_coord(int d) {
-  return d == 1 ? 24 : (d == 2 ? 16 : (d == 3 ? 10 : 8));
+  return d == 1 ? 24 : (d == 2 ? 12 : (d == 3 ? 10 : 8));
 }
 
 // Scalars of one sweep (passed by value; SGPRs in the kernels).

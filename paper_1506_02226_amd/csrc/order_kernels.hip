@@ -132,6 +132,7 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int *__restrict__ hist, int 
   const int per = (ntiles + 3) / 4;
   const int t0 = sgm * per, t1 = min(t0 + per, ntiles);
   int sum = 0;
+#pragma unroll 8
   for (int t = t0; t < t1; ++t) sum += hist[(long long)t * 256 + g];
   seg[sgm][g] = sum;
   __syncthreads();
@@ -146,11 +147,16 @@ __global__ __launch_bounds__(1024) void k_sort_scan(int *__restrict__ hist, int 
   }
   int run = (g ? base[g - 1] : 0);
   for (int k = 0; k < sgm; ++k) run += seg[k][g];
-  for (int t = t0; t < t1; ++t) {
-    const long long e = (long long)t * 256 + g;
-    const int v = hist[e];
-    hist[e] = run;
-    run += v;
+  // eight loads in flight at a time (the loop is bound by load latency)
+  for (int t = t0; t < t1; t += 8) {
+    int v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = t + u < t1 ? hist[(long long)(t + u) * 256 + g] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (t + u < t1) hist[(long long)(t + u) * 256 + g] = run;
+      run += v[u];
+    }
   }
 }
 
