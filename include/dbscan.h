@@ -85,8 +85,8 @@ extern "C" {
 #define DBSCAN_PREC_AUTO 0 /* FP16 matrix cores for 16 <= d <= 76, else float32 */
 #define DBSCAN_PREC_FP32 1 /* float32 direct form (x_i - x_j)^2 summed */
 #define DBSCAN_PREC_BF16 2 /* |x|^2 + |y|^2 - 2 x.y on BF16 matrix cores, d <= 76 */
-#define DBSCAN_PREC_FP16 3 /* same on FP16 matrix cores, d <= 76; inputs with
-                              |x| > 30000 or |x|^2 > 30000 fall back to float32 */
+#define DBSCAN_PREC_FP16 3 /* same on FP16 matrix cores, d <= 76; inputs with a
+                              coordinate |x| > 30000 fall back to float32 */
 
 typedef struct dbscan_opts {
   int32_t adjacency;          /* DBSCAN_ADJ_*  (0 = auto) */

@@ -42,11 +42,18 @@ template <> struct LowPrec<_Float16> {
 
 // ---------------------------------------------------------------- prepare
 // A block prepares 256 (padded) points, each wave 64 of them one after the
-// other with the lanes over the coordinates (coalesced loads and stores):
-// rounded coordinates, the FP32 norm of the rounded point (a wave sum, split
-// hi + lo), both augmented rows, and the float64 norm of the original point
+// other with the lanes over the coordinates (coalesced loads and stores): the
+// rounded coordinates x~ (row of a_aug, zero-padded to K), -2 x~ (row of
+// b_aug), the FP32 norm of the rounded point (a wave sum; +inf for padded
+// rows, so that no padded pair can reach the band) in the float array that
+// follows the n_pad rows of a_aug, and the float64 norm of the original point
 // for the bounds (max via an atomic on its bit pattern).  K <= 128.  With a
-// spatial order, row i of the augmented copies is input row perm[i].
+// spatial order, row i of the copies is input row perm[i].
+template <typename T>
+__device__ __forceinline__ const float *mfma_norms(const T *a_aug, int n_pad, int K) {
+  return reinterpret_cast<const float *>(a_aug + (size_t)n_pad * K);
+}
+
 template <typename T>
 __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, int n, int d,
                                                int n_pad, int K, T *__restrict__ a_aug,
@@ -54,6 +61,7 @@ __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, in
                                                const int *__restrict__ perm = nullptr) {
   const int lane = lane_id();
   const int w = (int)(threadIdx.x >> 6);
+  float *norms = const_cast<float *>(mfma_norms<T>(a_aug, n_pad, K));
   bool bad = false, nonfinite = false;
   double mx = 0.0;
   for (int t = 0; t < 64; ++t) {
@@ -78,7 +86,7 @@ __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, in
           part64 += (double)x * (double)x;
           a[k] = xr;
           b[k] = (T)(-2.0f * xf);
-        } else if (k >= d + 4 && k < K) {
+        } else if (k < K) {
           a[k] = (T)0.0f;
           b[k] = (T)0.0f;
         }
@@ -88,41 +96,18 @@ __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, in
         part += __shfl_xor(part, off);
         part64 += __shfl_xor(part64, off);
       }
-      const float nrm = part;  // same value in every lane
-      bad |= !(nrm <= LowPrec<T>::maxval);
-      const T hi = (T)nrm;
-      const T lo = (T)(nrm - (float)hi);
-      if (lane == 0) {
-        a[d] = hi;
-        a[d + 1] = lo;
-        a[d + 2] = (T)1.0f;
-        a[d + 3] = (T)1.0f;
-        b[d] = (T)1.0f;
-        b[d + 1] = (T)1.0f;
-        b[d + 2] = hi;
-        b[d + 3] = lo;
-      }
+      if (lane == 0) norms[i] = part;  // same value in every lane
       mx = part64 > mx ? part64 : mx;
     } else {
-      // padding: a norm so large that no padded pair can reach the band
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = lane + 64 * h;
-        if (k < K && (k < d || k >= d + 4)) {
+        if (k < K) {
           a[k] = (T)0.0f;
           b[k] = (T)0.0f;
         }
       }
-      if (lane == 0) {
-        a[d] = (T)LowPrec<T>::big;
-        a[d + 1] = (T)0.0f;
-        a[d + 2] = (T)1.0f;
-        a[d + 3] = (T)1.0f;
-        b[d] = (T)1.0f;
-        b[d + 1] = (T)1.0f;
-        b[d + 2] = (T)LowPrec<T>::big;
-        b[d + 3] = (T)0.0f;
-      }
+      if (lane == 0) norms[i] = __builtin_inff();
     }
   }
   if (lane == 0 && mx > 0.0)
@@ -144,10 +129,13 @@ __device__ __forceinline__ float next_up(float x) { return -next_down(-x); }
 //   |x - x~| <= u |x| + sqrt(d) tiny per point, so |D - D~| <= Delta with
 //   Delta = 2 (u M + sqrt(d) tiny), M = max |x_i| (D = |x_i - x_j| exact,
 //   D~ the same for the rounded points);
-//   |s~ - D~^2| <= E = c (|x~_i|^2 + |x~_j|^2) with c covering the FP32 norm
-//   (gamma_d), its hi+lo split and the FP32 accumulation of the 2K-term
-//   contraction counted twice (the matrix core's internal order is not
-//   specified); |x~|^2 <= (M(1+u) + sqrt(d) tiny)^2;
+//   |s~ - D~^2| <= E = c (|x~_i|^2 + |x~_j|^2) with c covering the FP32 norms
+//   (gamma_d), the FP32 sum of the two norms that starts the accumulation
+//   (within the 4u^2 + 2u32 kept from a hi+lo split of the norms, which the
+//   rounding of that sum does not exceed) and the FP32 accumulation of the
+//   K-term contraction onto it (bounded with 2K+2 terms, counted twice: the
+//   matrix core's internal order is not specified);
+//   |x~|^2 <= (M(1+u) + sqrt(d) tiny)^2;
 //   the float64 definition decides in when S <= eps2 (1 - 2 g64) and out when
 //   S >= eps2 (1 + 2 g64), g64 = (d+2) 2^-53.
 // In: s~ <= (eps_in - Delta)^2 - E.  Out: s~ > (eps_out + Delta)^2 + E.  The
@@ -201,6 +189,7 @@ template <int KS>
 struct MfmaLds {
   static constexpr int kPitch = 2 * KS + 1;
   uint4 atile[3][32 * kPitch];
+  float anorm[3][32];  // FP32 norms of the a-tile's rows
   int2 qpair[4][kListQueue];
   int2 qband[4][kBandQueue];
   // row-side counts of the item's rows, two 16-bit counts per word (a row
@@ -251,14 +240,18 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
       __hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kStatusRange;
   if (range_bad || rt0 >= rt1) return;  // uniform over the work-group
 
-  // stationary b-fragments: lane l holds b[8*(l/32) + 16 s .. +7] of column l%32
+  // stationary b-fragments: lane l holds b[8*(l/32) + 16 s .. +7] of column
+  // l%32, and that column's norm
+  const float *norms = mfma_norms<T>(a_aug, sc.n_pad, K);
   V bfr[2][KS];
+  float cn[2];
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int j = col0 + c * 32 + (lane & 31);
     const V *src = (const V *)(b_aug + (size_t)j * K);
 #pragma unroll
     for (int s = 0; s < KS; ++s) bfr[c][s] = src[2 * s + (lane >> 5)];
+    cn[c] = norms[j];
   }
   // wait for them here: inside the loop only the next a-tile's loads are in
   // flight, so the matrix-core work never waits on global memory
@@ -278,6 +271,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   // and the epilogue.
   constexpr int kChunks = 32 * 2 * KS;
   constexpr int kPer = (kChunks + 255) / 256;  // chunks per thread (1 or 2)
+  float pre_n = 0.0f;  // threads 0..31: the norm of row tid of the fetched tile
   auto fetch = [&](V(&pre)[kPer], int rt) {
     const V *src = (const V *)(a_aug + (size_t)rt * 32 * K);
 #pragma unroll
@@ -285,6 +279,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
       const int e = tid + 256 * u;
       pre[u] = src[e < kChunks ? e : kChunks - 1];  // unconditional: no branch
     }
+    pre_n = norms[rt * 32 + (tid & 31)];
   };
   auto stash = [&](const V(&pre)[kPer], int buf) {
 #pragma unroll
@@ -295,13 +290,28 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
         atile[buf][row * kPitch + ch] = pre[u];
       }
     }
+    if (tid < 32) lds.anorm[buf][tid] = pre_n;
   };
   auto tile = [&](int rt, int buf) {
     V afr[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(lane & 31) * kPitch + 2 * s + (lane >> 5)];
+    // the accumulators start at |x~_i|^2 + |x~_j|^2: accumulator r of this
+    // lane is row 4 (lane / 32) + 8 (r / 4) + r % 4, column lane % 32
+    f32x16 acc0, acc1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4 rn = *reinterpret_cast<const float4 *>(&lds.anorm[buf][4 * (lane >> 5) + 8 * q]);
+      acc0[4 * q] = rn.x + cn[0];
+      acc0[4 * q + 1] = rn.y + cn[0];
+      acc0[4 * q + 2] = rn.z + cn[0];
+      acc0[4 * q + 3] = rn.w + cn[0];
+      acc1[4 * q] = rn.x + cn[1];
+      acc1[4 * q + 1] = rn.y + cn[1];
+      acc1[4 * q + 2] = rn.z + cn[1];
+      acc1[4 * q + 3] = rn.w + cn[1];
+    }
     // two independent accumulation chains, interleaved
-    f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       acc0 = LowPrec<T>::mfma(afr[s], bfr[0][s], acc0);

@@ -21,7 +21,7 @@ constexpr double kDefaultBandRel = 1e-2;
 constexpr uint64_t kPairsPerPoint = 128;       // default pair-list capacity per point
 constexpr uint64_t kMaxPairs = 2147483647ull;  // 16 GiB of (int, int) pairs
 constexpr uint64_t kBandPerPoint = 64;         // default band-list capacity per point
-constexpr int32_t kMaxMfmaD = 76;              // contraction d + 4 <= 80
+constexpr int32_t kMaxMfmaD = 76;              // contraction length <= 80
 constexpr int64_t kSpatialMinN = 65536;        // auto order: below this the sort's ~15
                                                // launches cost more than they save
 
@@ -120,7 +120,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   L->off_pairs = L->edge_cap ? take((uint64_t)L->edge_cap * 8) : off;
   if (mfma) {
     L->mfma_k = dbk::mfma_k(d);
-    L->off_aaug = take((uint64_t)L->n_pad * L->mfma_k * 2);
+    L->off_aaug = take(dbk::mfma_a_bytes(L->n_pad, L->mfma_k));
     L->off_baug = take((uint64_t)L->n_pad * L->mfma_k * 2);
     const uint64_t req = (o && o->band_capacity) ? o->band_capacity : (uint64_t)kBandPerPoint * n;
     L->band_cap = (int64_t)(req < kMaxPairs ? req : kMaxPairs);

@@ -99,6 +99,11 @@ hipError_t run_filter_fallback(const float *pts, const int *perm, int n, int d, 
                                int d_pad, float *soa, int *counts, DevState *st, hipStream_t s);
 
 int mfma_k(int d);
+// Bytes of the a-rows of the matrix-core filter: n_pad rows of K 16-bit
+// values, then the n_pad FP32 norms.
+inline uint64_t mfma_a_bytes(int64_t n_pad, int K) {
+  return (uint64_t)n_pad * K * 2 + (uint64_t)n_pad * 4;
+}
 hipError_t run_mfma_prep(const float *pts, const int *perm, int n, int d, int n_pad, int prec,
                          void *a_aug, void *b_aug, DevState *st, hipStream_t s);
 hipError_t run_mfma_thresholds(DevState *st, double eps2, int d, int prec, double band_rel,

@@ -5,12 +5,11 @@
 // inner loop: dist(t, p) = T + P[n] - (X p_x + Y p_y + Z p_z) with T = |t|^2,
 // P[n] = |p|^2 and (X, Y, Z) = 2t.  Here the same expansion,
 // |x_i|^2 + |x_j|^2 - 2 x_i.x_j, is evaluated for 32x32 tiles of pairs on the
-// matrix cores, with the two squared norms folded into the contraction as
-// extra coordinates:
-//   a_i = [x~_i, nhi_i, nlo_i, 1, 1, 0...],  b_j = [-2 x~_j, 1, 1, nhi_j, nlo_j, 0...]
-// so that a_i . b_j = |x~_i|^2 + |x~_j|^2 - 2 x~_i.x~_j (x~ = x rounded to
-// BF16/FP16, n = the FP32 squared norm of x~ split into a high and a low
-// BF16/FP16 part).  The result is only a filter: with the rigorous bounds of
+// matrix cores: each accumulator starts at n_i + n_j (the FP32 squared norms
+// of the rounded points, the hoisted T and P[n]) and the contraction of
+//   a_i = [x~_i, 0...],  b_j = [-2 x~_j, 0...]  (K = d rounded up to 16)
+// is added onto it, so that s~ = n_i + n_j - 2 x~_i.x~_j (x~ = x rounded to
+// BF16/FP16).  The result is only a filter: with the rigorous bounds of
 // k_mfma_thresholds a pair is "in" when s~ <= T_lo, "out" when s~ > T_hi, and
 // every pair in between is queued and re-decided in float64 from the FP32
 // inputs with the definition's own arithmetic (k_recheck_band).  Decisions,
@@ -83,7 +82,7 @@ __global__ __launch_bounds__(256) void k_recheck_band(const float *__restrict__ 
 }
 
 // ------------------------------------------------------------ host launchers
-int mfma_k(int d) { return (d + 4 + 15) / 16 * 16; }
+int mfma_k(int d) { return (d + 15) / 16 * 16; }
 
 hipError_t run_mfma_prep(const float *pts, const int *perm, int n, int d, int n_pad, int prec,
                          void *a_aug, void *b_aug, DevState *st, hipStream_t s) {

@@ -118,7 +118,7 @@ ServeLayout serve_layout(const dbscan_job &j) {
   L.off_pairs = take((uint64_t)L.pair_cap * 8);
   if (L.prec == DBSCAN_PREC_FP16) {
     L.ks = dbk::mfma_k(d) / 16;
-    L.off_aaug = take((uint64_t)L.n_pad * L.ks * 16 * 2);
+    L.off_aaug = take(dbk::mfma_a_bytes(L.n_pad, L.ks * 16));
     L.off_baug = take((uint64_t)L.n_pad * L.ks * 16 * 2);
     L.band_cap = (int64_t)(kServeBandPerPoint * (uint64_t)j.n);
     L.off_band = take((uint64_t)L.band_cap * 8);

@@ -83,11 +83,12 @@ def test_workspace_size_layout():
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(wide), ctypes.byref(out)) == 0
     assert 8 * 128 * 100_000 < out.value < 8 * 128 * 100_000 + 32 * 100_096 * 4
     plain = out.value
-    # matrix cores (auto for 16 <= d <= 76): + two augmented copies (K = 32 here,
-    # 2 bytes each) and 64 band entries per point, 8 bytes each
+    # matrix cores (auto for 16 <= d <= 76): + two 16-bit copies of the rows
+    # (K = d rounded up to 16 = 16 here), the float32 norms and 64 band
+    # entries per point, 8 bytes each
     mc = _lib.make_opts("onthefly", "auto", order="input")
     assert L.dbscan_workspace_size(100_000, 16, ctypes.byref(mc), ctypes.byref(out)) == 0
-    extra = 2 * 100_096 * 32 * 2 + 8 * 64 * 100_000
+    extra = 2 * 100_096 * 16 * 2 + 100_096 * 4 + 8 * 64 * 100_000
     assert out.value - plain == extra
     big_d = _lib.make_opts("auto", "bf16")
     assert L.dbscan_workspace_size(1000, 77, ctypes.byref(big_d), ctypes.byref(out)) == _lib.DBSCAN_E_UNSUPPORTED

@@ -305,12 +305,21 @@ def test_mfma_band_overflow_and_range_fallback(prec):
     gpu = run(w.points, w.eps, w.minpts, precision=prec, pair_capacity=5, stats=True)
     assert gpu[3]["pair_overflow"] == 1
     assert_same(gpu, ref, "pair overflow")
-    if prec == "fp16":  # coordinates beyond the FP16 range of the filter
-        big = (w.points * 3000.0).astype(np.float32)
-        refb = c_oracle.dbscan(big, w.eps * 3000.0, w.minpts)
-        gpu = run(big, w.eps * 3000.0, w.minpts, precision=prec, stats=True)
+    if prec == "fp16":
+        # coordinates beyond the FP16 range of the filter (|x| <= 30000)
+        big = (w.points * 10000.0).astype(np.float32)
+        assert np.abs(big).max() > 30000.0
+        refb = c_oracle.dbscan(big, w.eps * 10000.0, w.minpts)
+        gpu = run(big, w.eps * 10000.0, w.minpts, precision=prec, stats=True)
         assert gpu[3]["filter_fallback"] == 1
         assert_same(gpu, refb, "range")
+        # large but in range: the norms are float32, so the filter still runs
+        mid = (w.points * 3000.0).astype(np.float32)
+        assert np.abs(mid).max() < 30000.0
+        refm = c_oracle.dbscan(mid, w.eps * 3000.0, w.minpts)
+        gpu = run(mid, w.eps * 3000.0, w.minpts, precision=prec, stats=True)
+        assert gpu[3]["filter_fallback"] == 0
+        assert_same(gpu, refm, "large in range")
 
 
 @pytest.mark.parametrize("prec", PRECS + ("fp32",))

@@ -100,8 +100,8 @@ def test_served_rejects_and_fallbacks():
         pn = rng.uniform(0, 1, size=(300, 2)).astype(np.float32)
         pn[7, 0] = np.inf
         jn = srv.submit(_gpu(pn), 0.1, 3)
-        # squared norms beyond the half-precision range: the filter gives up
-        pw = rng.uniform(0, 200, size=(400, 16)).astype(np.float32)
+        # coordinates beyond the half-precision range: the filter gives up
+        pw = rng.uniform(0, 40000, size=(400, 16)).astype(np.float32)
         pw[:200] = pw[0] + rng.normal(0, 1, size=(200, 16)).astype(np.float32)
         jw = srv.submit(_gpu(pw), 4.0, 5)
         s8, sd, sn, sw = srv.wait(j8), srv.wait(jd), srv.wait(jn), srv.wait(jw)
