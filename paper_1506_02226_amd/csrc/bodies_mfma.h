@@ -130,11 +130,11 @@ __device__ __forceinline__ float next_up(float x) { return -next_down(-x); }
 //   Delta = 2 (u M + sqrt(d) tiny), M = max |x_i| (D = |x_i - x_j| exact,
 //   D~ the same for the rounded points);
 //   |s~ - D~^2| <= E = c (|x~_i|^2 + |x~_j|^2) with c covering the FP32 norms
-//   (gamma_d), the FP32 sum of the two norms that starts the accumulation
-//   (within the 4u^2 + 2u32 kept from a hi+lo split of the norms, which the
-//   rounding of that sum does not exceed) and the FP32 accumulation of the
-//   K-term contraction onto it (bounded with 2K+2 terms, counted twice: the
-//   matrix core's internal order is not specified);
+//   (gamma_d) and the FP32 sum of the K exact products (-2 x~_ik x~_jk) and
+//   the two norms: the contraction accumulates onto n_i in the matrix core
+//   (whose internal order is not specified) and n_j is added last, K+2 terms
+//   whose absolute sum is at most 2 (n_i + n_j), bounded here with
+//   gamma_{2K+2} counted twice; the 4u^2 + 2u32 term is further slack;
 //   |x~|^2 <= (M(1+u) + sqrt(d) tiny)^2;
 //   the float64 definition decides in when S <= eps2 (1 - 2 g64) and out when
 //   S >= eps2 (1 + 2 g64), g64 = (d+2) 2^-53.
@@ -296,24 +296,24 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
     V afr[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) afr[s] = atile[buf][(lane & 31) * kPitch + 2 * s + (lane >> 5)];
-    // the accumulators start at |x~_i|^2 + |x~_j|^2: accumulator r of this
-    // lane is row 4 (lane / 32) + 8 (r / 4) + r % 4, column lane % 32
-    f32x16 acc0, acc1;
+    // the accumulators start at |x~_i|^2 (the matrix core reads the row
+    // norms as its addend; accumulator r of this lane is row
+    // 4 (lane / 32) + 8 (r / 4) + r % 4, column lane % 32) and |x~_j|^2 is
+    // added after the contraction, so s~ = (n_i - 2 x~_i.x~_j) + n_j
+    f32x16 rn;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const float4 rn = *reinterpret_cast<const float4 *>(&lds.anorm[buf][4 * (lane >> 5) + 8 * q]);
-      acc0[4 * q] = rn.x + cn[0];
-      acc0[4 * q + 1] = rn.y + cn[0];
-      acc0[4 * q + 2] = rn.z + cn[0];
-      acc0[4 * q + 3] = rn.w + cn[0];
-      acc1[4 * q] = rn.x + cn[1];
-      acc1[4 * q + 1] = rn.y + cn[1];
-      acc1[4 * q + 2] = rn.z + cn[1];
-      acc1[4 * q + 3] = rn.w + cn[1];
+      const float4 v = *reinterpret_cast<const float4 *>(&lds.anorm[buf][4 * (lane >> 5) + 8 * q]);
+      rn[4 * q] = v.x;
+      rn[4 * q + 1] = v.y;
+      rn[4 * q + 2] = v.z;
+      rn[4 * q + 3] = v.w;
     }
     // two independent accumulation chains, interleaved
+    f32x16 acc0 = LowPrec<T>::mfma(afr[0], bfr[0][0], rn);
+    f32x16 acc1 = LowPrec<T>::mfma(afr[0], bfr[1][0], rn);
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
+    for (int s = 1; s < KS; ++s) {
       acc0 = LowPrec<T>::mfma(afr[s], bfr[0][s], acc0);
       acc1 = LowPrec<T>::mfma(afr[s], bfr[1][s], acc1);
     }
@@ -322,15 +322,17 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const f32x16 acc = c ? acc1 : acc0;
-      // one test per tile: does any pair of this lane reach the band?
+      // one test per tile: does any pair of this lane reach the band?  The
+      // FP32 addition of n_j is monotone, so (min_r a_r) + n_j is the
+      // smallest of the lane's 16 values a_r + n_j
       float mn = acc[0];
 #pragma unroll
       for (int r = 1; r < 16; ++r) mn = __builtin_fminf(mn, acc[r]);
-      if (__ballot(mn <= t_hi) == 0ull) continue;
+      if (__ballot(mn + cn[c] <= t_hi) == 0ull) continue;
       const int j = col0 + c * 32 + (lane & 31);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const float v = acc[r];
+        const float v = acc[r] + cn[c];
         if (__ballot(v <= t_hi) != 0ull) {
           const int i = row_base + 8 * (r >> 2) + (r & 3);
           const bool valid = i < sc.n && j < sc.n;

@@ -5,11 +5,11 @@
 // inner loop: dist(t, p) = T + P[n] - (X p_x + Y p_y + Z p_z) with T = |t|^2,
 // P[n] = |p|^2 and (X, Y, Z) = 2t.  Here the same expansion,
 // |x_i|^2 + |x_j|^2 - 2 x_i.x_j, is evaluated for 32x32 tiles of pairs on the
-// matrix cores: each accumulator starts at n_i + n_j (the FP32 squared norms
-// of the rounded points, the hoisted T and P[n]) and the contraction of
+// matrix cores: each accumulator starts at n_i (the FP32 squared norm of the
+// rounded row point, the hoisted T), the contraction of
 //   a_i = [x~_i, 0...],  b_j = [-2 x~_j, 0...]  (K = d rounded up to 16)
-// is added onto it, so that s~ = n_i + n_j - 2 x~_i.x~_j (x~ = x rounded to
-// BF16/FP16).  The result is only a filter: with the rigorous bounds of
+// is added onto it, and the column's n_j (P[n]) is added to the result, so
+// that s~ = n_i - 2 x~_i.x~_j + n_j (x~ = x rounded to BF16/FP16).  The result is only a filter: with the rigorous bounds of
 // k_mfma_thresholds a pair is "in" when s~ <= T_lo, "out" when s~ > T_hi, and
 // every pair in between is queued and re-decided in float64 from the FP32
 // inputs with the definition's own arithmetic (k_recheck_band).  Decisions,
