@@ -215,16 +215,16 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int w = wave_uniform(tid >> 6);
-  // item -> (column group, chunk); sc.chunk is a multiple of 8 row tiles
+  // item -> (chunk, column group); sc.chunk is a multiple of 8 row tiles
   const int G = sc.n_pad / kMfmaColsPerGroup, kpc = sc.chunk / 8;
-  int lo = 0, hi = G - 1;
-  while (lo < hi) {  // last column group whose first item is <= bid
+  int lo = 0, hi = sc.nchunks - 1;
+  while (lo < hi) {  // last chunk whose first item is <= bid
     const int mid = (lo + hi + 1) >> 1;
-    if (mfma_items_before(mid, sc.nchunks, kpc) <= bid) lo = mid;
+    if (mfma_items_before_chunk(mid, G, kpc) <= bid) lo = mid;
     else hi = mid - 1;
   }
-  const int cgroup = lo;
-  const int chunk = lo / kpc + (bid - (int)mfma_items_before(lo, sc.nchunks, kpc));
+  const int chunk = lo;
+  const int cgroup = bid - (int)mfma_items_before_chunk(lo, G, kpc);
   const int col0 = cgroup * kMfmaColsPerGroup + w * kMfmaColsPerWave;
   // Lower triangle only: row tiles from the group's own columns onwards.  The
   // 8 row tiles that overlap the group's 256 columns (the diagonal zone) are

@@ -67,11 +67,20 @@ struct MfmaScalars {
 
 // Work items of the triangular matrix-core sweep: (column group g of 256
 // columns, row chunk c of 8k row tiles of 32) with c >= g / k (integer
-// division), listed column group by column group, so that blocks running at
-// the same time share columns and spread over rows.  Items before group g:
+// division).  Their number, counted column group by column group (items
+// before group g):
 __host__ __device__ inline long long mfma_items_before(int g, int nchunks, int k) {
   const long long q = g / k, r = g - q * k;
   return (long long)g * nchunks - (k * q * (q - 1) / 2 + q * r);
+}
+// They are listed row chunk by row chunk: chunk c holds the groups
+// 0 .. min(G, (c+1) k) - 1, so that items running at the same time share
+// their rows (one chunk's a-tiles serve many column groups from L2).  Items
+// before chunk c:
+__host__ __device__ inline long long mfma_items_before_chunk(int c, int G, int k) {
+  const long long c1 = G / k;  // chunks below c1 hold (c+1) k <= G groups
+  if (c <= c1) return (long long)k * c * (c + 1) / 2;
+  return (long long)k * c1 * (c1 + 1) / 2 + (long long)(c - c1) * G;
 }
 
 int rows_per_wave(int d);

@@ -56,7 +56,13 @@ __global__ __launch_bounds__(256) void k_mfma_count(const T *__restrict__ a_aug,
                                                     int2 *__restrict__ band,
                                                     DevState *__restrict__ st, MfmaScalars sc) {
   __shared__ MfmaLds<KS> lds;
-  mfma_count_body<T, KS>(a_aug, b_aug, counts, pairs, band, st, sc, blockIdx.x, lds);
+  // consecutive work-groups are dealt round-robin to the 8 XCDs: renumber
+  // them so that each XCD runs one contiguous range of items (rows shared in
+  // its L2)
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned per = nb / 8, rem = nb % 8, x = b % 8, q = b / 8;
+  const unsigned item = x < rem ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+  mfma_count_body<T, KS>(a_aug, b_aug, counts, pairs, band, st, sc, (int)item, lds);
 }
 
 // ------------------------------------------------------- float64 band pass
