@@ -182,7 +182,7 @@ constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 // 2KS+1 chunks: the pitch is odd, so the 16 rows that one pass of a 16-byte
 // read touches fall in 16 distinct bank groups (no conflicts), and the
 // writes, which follow the global row-major order, stay nearly conflict-free.
-constexpr int kMfmaChunkTiles = 64;   // row tiles of 32 per work item, at most
+constexpr int kMfmaChunkTiles = 128;  // row tiles of 32 per work item, at most
 constexpr int kBandQueue = 128;       // band queue (pairs); appended 64 at a time
 
 template <int KS>

@@ -425,9 +425,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     ms.n = ni;
     ms.n_pad = npad;
     ms.d = d;
-    // row chunks of 64 tiles (2048 rows; fewer for small n), 8 per column group
+    // row chunks of 128 tiles (4096 rows; fewer for small n), 16 per column group
     const int tiles = (int)(npad / 32);
-    ms.chunk = tiles < 64 ? tiles : 64;
+    ms.chunk = tiles < 128 ? tiles : 128;
     ms.nchunks = (tiles + ms.chunk - 1) / ms.chunk;
     ms.pair_cap = L.edge_cap;
     ms.band_cap = L.band_cap;
