@@ -316,10 +316,10 @@ void dbscan_server::loop() {
       js.ntasks[dbk::kPhStage] = blocks256;
       js.ntasks[dbk::kPhThresh] = L.ks ? 1u : 0u;
       if (L.ks) {
-        // 256 stationary columns per task, row chunks of <= 64 tiles of 32
+        // 256 stationary columns per task, row chunks of <= 128 tiles of 32
         // rows; only the lower triangle of (chunk, column group) is a task
         const int tiles = L.n_pad / 32;
-        const int per = tiles < 64 ? tiles : 64;
+        const int per = tiles < 128 ? tiles : 128;
         jd.chunk = per;
         jd.nchunks = (tiles + per - 1) / per;
         js.ntasks[dbk::kPhCount] =
