@@ -177,7 +177,7 @@ constexpr int kMfmaColsPerWave = 64;                   // two 32-column tiles
 constexpr unsigned kBandBoth = 0x80000000u;            // band entry flag (row index bit 31)
 constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 
-// LDS for one block of the tile sweep: three a-tiles and the pair/band queues.
+// LDS for one block of the tile sweep: two a-tiles and the pair/band queues.
 // An a-tile is 32 rows of 2KS 16-byte chunks, row-major with a pitch of
 // 2KS+1 chunks: the pitch is odd, so the 16 rows that one pass of a 16-byte
 // read touches fall in 16 distinct bank groups (no conflicts), and the
@@ -188,8 +188,8 @@ constexpr int kBandQueue = 128;       // band queue (pairs); appended 64 at a ti
 template <int KS>
 struct MfmaLds {
   static constexpr int kPitch = 2 * KS + 1;
-  uint4 atile[3][32 * kPitch];
-  float anorm[3][32];  // FP32 norms of the a-tile's rows
+  uint4 atile[2][32 * kPitch];
+  float anorm[2][32];  // FP32 norms of the a-tile's rows
   int2 qpair[4][kListQueue];
   int2 qband[4][kBandQueue];
   // row-side counts of the item's rows, two 16-bit counts per word (a row
@@ -263,12 +263,13 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   for (int k = tid; k < sc.chunk * 16; k += 256) lds.rowcnt[k] = 0u;  // before the first barrier
 
   // cooperative a-tile load: 32 rows x 2KS 16-byte chunks (coalesced).
-  // Three LDS buffers: at the top of iteration t, tile t+1 (fetched into
-  // registers one iteration earlier) is written to buffer (t+1)%3 and tile t+2
-  // is fetched, then tile t is computed from buffer t%3; one barrier per
-  // iteration.  A global load has a whole iteration to land before its
-  // registers are written out, and no wait sits between the matrix-core work
-  // and the epilogue.
+  // Two LDS buffers: at the top of iteration t, tile t+1 (fetched into
+  // registers one iteration earlier) is written to buffer (t+1)%2 and tile t+2
+  // is fetched, then tile t is computed from buffer t%2; one barrier per
+  // iteration.  Buffer (t+1)%2 last held tile t-1, which every wave finished
+  // before the barrier that ended iteration t-1.  A global load has a whole
+  // iteration to land before its registers are written out, and no wait sits
+  // between the matrix-core work and the epilogue.
   constexpr int kChunks = 32 * 2 * KS;
   constexpr int kPer = (kChunks + 255) / 256;  // chunks per thread (1 or 2)
   float pre_n = 0.0f;  // threads 0..31: the norm of row tid of the fetched tile
@@ -364,7 +365,7 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   __syncthreads();
   int bcur = 0;
   for (int rt = rt0; rt < rt1; ++rt) {
-    const int bnext = bcur == 2 ? 0 : bcur + 1;
+    const int bnext = bcur ^ 1;
     if (rt + 1 < rt1) stash(pre, bnext);
     if (rt + 2 < rt1) fetch(pre, rt + 2);
     tile(rt, bcur);
