@@ -182,7 +182,6 @@ constexpr int kMfmaColsPerGroup = 4 * kMfmaColsPerWave;  // 256
 // 2KS+1 chunks: the pitch is odd, so the 16 rows that one pass of a 16-byte
 // read touches fall in 16 distinct bank groups (no conflicts), and the
 // writes, which follow the global row-major order, stay nearly conflict-free.
-constexpr int kMfmaChunkTiles = 128;  // row tiles of 32 per work item, at most
 constexpr int kBandQueue = 128;       // band queue (pairs); appended 64 at a time
 
 template <int KS>
@@ -194,7 +193,7 @@ struct MfmaLds {
   int2 qband[4][kBandQueue];
   // row-side counts of the item's rows, two 16-bit counts per word (a row
   // meets at most 256 columns in one item)
-  unsigned rowcnt[kMfmaChunkTiles * 32 / 2];
+  unsigned rowcnt[mfma_chunk_tiles(KS) * 32 / 2];
   unsigned long long xfer[5];
 };
 

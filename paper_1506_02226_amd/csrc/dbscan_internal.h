@@ -73,6 +73,10 @@ __host__ __device__ inline long long mfma_items_before(int g, int nchunks, int k
   const long long q = g / k, r = g - q * k;
   return (long long)g * nchunks - (k * q * (q - 1) / 2 + q * r);
 }
+// Row tiles of 32 per matrix-core work item, at most: an item's row counts
+// sit in LDS, and at K <= 64 (ks <= 4) 256 tiles still leave room for four
+// work-groups per CU.
+__host__ __device__ constexpr int mfma_chunk_tiles(int ks) { return ks <= 4 ? 256 : 128; }
 // They are listed row chunk by row chunk: chunk c holds the groups
 // 0 .. min(G, (c+1) k) - 1, so that items running at the same time share
 // their rows (one chunk's a-tiles serve many column groups from L2).  Items

@@ -118,11 +118,11 @@ hipError_t run_mfma_thresholds(DevState *st, double eps2, int d, int prec, doubl
 hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b,
                           const MfmaScalars &sc, int prec, hipStream_t s) {
   const int groups = sc.n_pad / kMfmaColsPerGroup;
-  if (sc.chunk % 8 != 0 || sc.chunk <= 0 || sc.chunk > kMfmaChunkTiles ||
+  const int ks = mfma_k(sc.d) / 16;
+  if (sc.chunk % 8 != 0 || sc.chunk <= 0 || sc.chunk > mfma_chunk_tiles(ks) ||
       (long long)sc.nchunks * sc.chunk < sc.n_pad / 32)
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)mfma_items_before(groups, sc.nchunks, sc.chunk / 8)), block(256);
-  const int ks = mfma_k(sc.d) / 16;
 #define DBK_MFMA_CASE(KS)                                                                     \
   case KS:                                                                                    \
     if (prec == kPrecBf16)                                                                    \

@@ -24,6 +24,7 @@ constexpr int kIdlePolls = 256;    // idle polls (~0.2 us each) before a block l
 
 union ServeLds {
   MfmaLds<5> m;
+  MfmaLds<4> m4;  // the largest row-count array: the union covers every MfmaLds<KS>
   int2 q[4][128];
   struct {
     int2 q[4][kListQueue];
@@ -61,6 +62,7 @@ __device__ __forceinline__ SweepScalars plain_scalars(const JobDesc &jd) {
 
 template <int KS>
 __device__ __forceinline__ void mfma_count_task(const JobDesc &jd, int idx, ServeLds &lds) {
+  static_assert(sizeof(MfmaLds<KS>) <= sizeof(ServeLds), "served LDS too small");
   MfmaScalars ms{};
   ms.n = jd.n;
   ms.n_pad = jd.n_pad;
