@@ -95,13 +95,11 @@ int oracle_dbscan(const float *x, int64_t n, int32_t d, double eps, int32_t minp
   for (int64_t i = 0; i < n; ++i) labels[i] = -1;
 
   int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-  uint8_t *hit = (uint8_t *)malloc((size_t)n);
-  if (!queue || !hit) {
-    free(queue);
-    free(hit);
-    return -2;
-  }
-  /* step 3: breadth-first search over core points, seeds in ascending order */
+  if (!queue) return -2;
+  /* step 3: breadth-first search over core points, seeds in ascending order.
+   * Every core point reached from seed s gets label s, whatever the order in
+   * which a level is queued: each q belongs to one iteration of the parallel
+   * loop, which labels it and takes the next queue slot atomically. */
   for (int64_t s = 0; s < n; ++s) {
     if (!core[s] || labels[s] != -1) continue;
     int64_t head = 0, tail = 0;
@@ -110,15 +108,18 @@ int oracle_dbscan(const float *x, int64_t n, int32_t d, double eps, int32_t minp
     while (head < tail) {
       const int64_t p = queue[head++];
       const float *xp = x + p * d;
+      int64_t next = tail;
 #pragma omp parallel for schedule(static)
-      for (int64_t q = 0; q < n; ++q)
-        hit[q] = core[q] && labels[q] == -1 && pair_sq(xp, x + q * d, d) <= eps2;
       for (int64_t q = 0; q < n; ++q) {
-        if (hit[q] && labels[q] == -1) {
+        if (core[q] && labels[q] == -1 && pair_sq(xp, x + q * d, d) <= eps2) {
+          int64_t slot;
           labels[q] = (int32_t)s;
-          queue[tail++] = q;
+#pragma omp atomic capture
+          slot = next++;
+          queue[slot] = q;
         }
       }
+      tail = next;
     }
   }
   /* border points: cluster of the lowest-index core neighbour */
@@ -134,7 +135,6 @@ int oracle_dbscan(const float *x, int64_t n, int32_t d, double eps, int32_t minp
     }
   }
   free(queue);
-  free(hit);
   return 0;
 }
 
