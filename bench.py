@@ -3,9 +3,9 @@
 
 One step = one full ``dbscan_fit`` (steps 1-3 of the paper: all-pairs epsilon
 test with neighbour counts and bitmask, core flags, union-find merge, border
-assignment, labels) on device-resident synthetic points.  Default workload:
-200,000 2-D points, 50 Gaussian blobs + 5% noise, eps=0.25, MinPts=10,
-bitmask adjacency.
+assignment, labels) on device-resident synthetic points.  Default workload: the largest
+configuration, 2,000,000 3-D points, 200 anisotropic Gaussian blobs + 5%
+noise, eps=0.4, MinPts=20, on-the-fly epsilon test (no stored adjacency).
 
 Prints one JSON line: whole-job epsilon-pair tests per second (n^2 per step),
 points clustered per second, the dominant kernel's roofline fraction (timed
@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 # probe measured 1.83 wave-instructions/clock/CU for independent v_mul_f32,
 # so the one-per-SIMD-every-4-clocks figure (39.3e12) is not a ceiling.
 VALU_LANE_OPS_PEAK = 256 * 128 * 2.4e9
+FP32_VECTOR_PEAK = 157.3e12  # published FP32 vector FLOP/s
 HBM_PEAK_BYTES = 8.0e12
 MFMA_16BIT_PEAK = 2.5e15  # dense BF16/FP16 matrix-core FLOP/s
 
@@ -42,6 +43,33 @@ def valu_ops_per_pair(d: int) -> int:
     without packed math: d subtractions, 1 multiply, d-1 fused multiply-adds
     and 1 compare."""
     return 2 * d + 1
+
+
+def flops_per_pair(d: int) -> int:
+    """Float32 direct form counted as floating-point operations: d
+    subtractions, d multiplies and d additions per pair test."""
+    return 3 * d
+
+
+# The paper's own headline, quoted as context (not a target): Table V, end to
+# end with host transfers, N = 60,032 three-dimensional points.
+PAPER_CONTEXT = {
+    "speedup_vs_cpu_with_transfer": 97.891, "speedup_vs_cpu_kernels": 175.70, "n": 60032,
+    "gpu_ms_with_transfer": 124.73, "cpu_ms": 12210,
+    "gpu": "NVIDIA Tesla K10.G2.8GB, one GK104 (8 SMX at 745 MHz, 3.76 GB)",
+    "cpu": "not stated (serial version)", "source": "Table V; Table II for the GPU",
+}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 class HipEvents:
@@ -94,22 +122,54 @@ def measured_traffic(kernel: str, workload: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(w, sample_n: int):
+def cpu_baseline(w, sample_n: int, single_n: int, row_sample: int):
+    """The C oracle as it stands, on bounded samples of the same workload.
+
+    value: the whole oracle (float64 counts, breadth-first merge, border rule)
+    on all host threads over the first `sample_n` points of the shuffled
+    workload (a uniform random subsample), rate m^2/t.  Beside it: the same
+    with one thread (the paper's serial comparator) on the first `single_n`
+    points, and the oracle's epsilon test and counts alone for `row_sample`
+    random rows against all n points (full density), rate rows*n/t."""
     from oracle import c_oracle
-    m = min(sample_n, w.n)
-    pts = np.ascontiguousarray(w.points[:m])
     threads = c_oracle.threads(0)
+
+    def whole(m, thr):
+        pts = np.ascontiguousarray(w.points[:min(m, w.n)])
+        t0 = time.perf_counter()
+        c_oracle.dbscan(pts, w.eps, w.minpts, threads=thr)
+        return pts.shape[0], time.perf_counter() - t0
+
+    m, dt = whole(sample_n, threads)
+    m1, dt1 = whole(single_n, 1)
+    c_oracle.threads(threads)
+    rows = np.sort(np.random.default_rng(7).choice(w.n, min(row_sample, w.n), replace=False))
     t0 = time.perf_counter()
-    c_oracle.dbscan(pts, w.eps, w.minpts, threads=threads)
-    dt = time.perf_counter() - t0
+    c_oracle.row_counts(w.points, w.eps, rows, threads=threads)
+    dtr = time.perf_counter() - t0
     return {
         "value": round(m * m / dt / 1e9, 4),
         "unit": "Gpairs/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": (f"full C oracle (float64 counts, BFS, border) on the first {m} points of the "
-                   f"shuffled workload (a uniform random subsample), {dt:.1f} s; rate = m^2/t"),
+        "sample": (f"whole C oracle (float64 counts, BFS merge, border) on the first {m} points of "
+                   f"the shuffled workload (a uniform random subsample), {dt:.1f} s on {threads} "
+                   f"threads; rate = m^2/t"),
+        "cpu_model": cpu_model(),
+        "single_thread": {"value": round(m1 * m1 / dt1 / 1e9, 4), "unit": "Gpairs/s", "cores": 1,
+                          "sample": f"whole C oracle, first {m1} points, {dt1:.1f} s"},
+        "step1_full_density": {"value": round(rows.size * w.n / dtr / 1e9, 4), "unit": "Gpairs/s",
+                               "cores": threads,
+                               "sample": (f"oracle epsilon test + counts for {rows.size} random "
+                                          f"rows x all {w.n} points, {dtr:.1f} s")},
     }
+
+
+# (all-threads, one-thread) oracle sample sizes per workload: each takes
+# roughly 5-20 s on the 16 host threads of one GPU's share.
+CPU_SAMPLES = {"aniso3d_2m": (200_000, 40_000), "blobs2d_200k": (120_000, 40_000),
+               "mix64d_300k": (40_000, 12_000), "mix64d_300k_q50": (40_000, 12_000),
+               "blobs2d_small": (2_000, 2_000)}
 
 
 def _gen_init():
@@ -225,14 +285,21 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="blobs2d_200k")
+    ap.add_argument("--workload", default="aniso3d_2m")
     ap.add_argument("--adjacency", default="auto", choices=["auto", "bitmask", "onthefly"])
     ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16", "fp16"])
     ap.add_argument("--order", default="auto", choices=["auto", "input", "spatial"])
     ap.add_argument("--prune", action="store_true",
                     help="tile pruning (skips tile pairs farther apart than eps): not every "
                          "pair is tested, so the line is not the all-pairs metric")
-    ap.add_argument("--cpu-sample", type=int, default=80_000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="points of the all-threads oracle sample (0: by workload)")
+    ap.add_argument("--cpu-single", type=int, default=0,
+                    help="points of the one-thread oracle sample (0: by workload)")
+    ap.add_argument("--cpu-rows", type=int, default=2000)
+    ap.add_argument("--transfer-steps", type=int, default=3,
+                    help="steps timed with the host-to-device copy of the points and the "
+                         "copy of the outputs back (pageable host memory)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for profiles)")
@@ -319,6 +386,10 @@ def main(argv=None) -> int:
                 "frac": round(achieved * 1e12 / VALU_LANE_OPS_PEAK, 4), "traffic": None,
                 "ops_per_test": valu_ops_per_pair(d), "tests_per_launch": int(tests),
                 "kernel_ms": round(k_ms, 4)}
+        fl = tests * flops_per_pair(d) / (k_ms * 1e-3)
+        roof["flop_basis"] = {"flops_per_test": flops_per_pair(d),
+                              "achieved": round(fl / 1e12, 3), "peak": FP32_VECTOR_PEAK / 1e12,
+                              "unit": "TFLOP/s", "frac": round(fl / FP32_VECTOR_PEAK, 4)}
     rec = {
         "metric": ("eps-pair decisions/sec with tile pruning (Gpairs/s) + points clustered/s"
                    if args.prune else "eps-pair tests/sec (Gpairs/s) + points clustered/s"),
@@ -345,9 +416,34 @@ def main(argv=None) -> int:
         "core_points": int(st["core_points"]),
         "roofline": roof,
     }
+    rec["tests_per_step"] = int(tests)
     roof["traffic"] = measured_traffic(roof["kernel"], w.name)
+
+    if args.transfer_steps > 0:
+        # Table V's "with data transmission" column: pageable host points in,
+        # outputs back to the host, every step
+        host = np.ascontiguousarray(w.points)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.transfer_steps):
+            xd = torch.from_numpy(host).to(dev)
+            pkg.fit(xd, w.eps, w.minpts, **kw)
+            res = [t.cpu() for t in out]
+        torch.cuda.synchronize()
+        ms_tr = (time.perf_counter() - t0) / args.transfer_steps * 1e3
+        rec["with_transfer"] = {"ms_per_step": round(ms_tr, 4),
+                                "points_per_s": round(n / (ms_tr * 1e-3), 1),
+                                "bytes_h2d": int(host.nbytes), "bytes_d2h": int(9 * n),
+                                "steps": args.transfer_steps}
+        del res
+    rec["paper_context"] = PAPER_CONTEXT
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        sample_n, single_n = CPU_SAMPLES.get(w.name, (80_000, 30_000))
+        cb = cpu_baseline(w, args.cpu_sample or sample_n, args.cpu_single or single_n,
+                          args.cpu_rows)
+        cb["gpu_speedup"] = round(rec["value"] / cb["value"], 1)
+        cb["gpu_speedup_single_thread"] = round(rec["value"] / cb["single_thread"]["value"], 1)
+        rec["cpu_baseline"] = cb
     print(json.dumps(rec), flush=True)
     return 0
 

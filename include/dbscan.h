@@ -60,8 +60,9 @@ extern "C" {
 #define DBSCAN_E_NONFINITE (-1001) /* a coordinate is NaN or +-inf */
 #define DBSCAN_E_UNSUPPORTED (-1002)
 
-/* Largest n accepted (indices and labels are int32). */
-#define DBSCAN_MAX_N 2147483583LL
+/* Largest n accepted: 2^31 - 256, so that n rounded up to a multiple of 256
+ * (the padded row count) is still an int32 index. */
+#define DBSCAN_MAX_N 2147483392LL
 
 /* How the neighbour relation is kept between step 2 and step 3. */
 #define DBSCAN_ADJ_AUTO 0     /* bitmask when it fits the limit, else on the fly */

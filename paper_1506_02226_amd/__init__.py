@@ -78,9 +78,10 @@ def fit(points, eps: float, minpts: int, *, adjacency: str = "auto", precision: 
         counts = torch.empty(n, dtype=torch.int32, device=dev)
     else:
         labels, core, counts = out
-    ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit, pair_capacity,
-                              band_capacity, order, prune)
     if workspace is None:
+        # a caller-supplied workspace is checked against the size by the library
+        ws_bytes = workspace_size(n, d, adjacency, precision, bitmask_limit, pair_capacity,
+                                  band_capacity, order, prune)
         workspace = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
     base = workspace.data_ptr()
     aligned = (base + 255) // 256 * 256

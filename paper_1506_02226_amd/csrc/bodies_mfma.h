@@ -22,7 +22,9 @@ template <> struct LowPrec<__bf16> {
   static constexpr double u = 0x1p-8;        // unit roundoff (8-bit significand)
   static constexpr double tiny = 0x1p-126;   // smallest normal
   static constexpr float big = 0x1p100f;     // padding norm: any padded pair is far
-  static constexpr float maxval = 3.0e38f;
+  // |x| bound of the filter: the FP32 norms and accumulators stay finite
+  // (4 K maxval^2 < FLT_MAX for K <= 128); larger inputs fall back to float32
+  static constexpr float maxval = 1.0e17f;
   __device__ static vec8 zero() { return vec8{}; }
   __device__ static f32x16 mfma(vec8 a, vec8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -165,7 +167,8 @@ __device__ __forceinline__ void mfma_thresholds_body(DevState *st, double eps2, 
   if (s_lo < t_lo) t_lo = s_lo;
   if (s_hi > t_hi) t_hi = s_hi;
   float lo = (float)t_lo, hi = (float)t_hi;
-  if (__builtin_isfinite(lo) && (double)lo > t_lo) lo = next_down(lo);
+  if (!__builtin_isfinite(lo)) lo = 0x1.fffffep127f;  // t_lo beyond FLT_MAX: round down
+  if ((double)lo > t_lo) lo = next_down(lo);
   if (__builtin_isfinite(hi) && (double)hi < t_hi) hi = next_up(hi);
   if (t_lo < 0.0) lo = -__builtin_inff();
   st->thr[0] = lo;

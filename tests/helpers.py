@@ -1,34 +1,46 @@
 """Shared checks of GPU results against the oracle (imported by the GPU test
 modules; not a test module itself)."""
+import json
+import os
+import sys
+
 import numpy as np
 
-from oracle import c_oracle
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+if GOLDEN_DIR not in sys.path:
+    sys.path.insert(0, GOLDEN_DIR)
+import make_full_size as mfs  # noqa: E402  (digest layout shared with the writer)
 
 
-def sampled_checks(w, gpu, rows):
-    """Exact per-row checks against the oracle at any size."""
-    lab, core, cnt = gpu[:3]
-    n = w.n
-    assert (core == (cnt >= w.minpts)).all()
-    ref_cnt = c_oracle.row_counts(w.points, w.eps, rows)
-    np.testing.assert_array_equal(cnt[rows], ref_cnt)
-    # canonical labels everywhere
-    nz = lab >= 0
-    assert (lab >= -1).all()
-    assert core[lab[nz]].all()
-    assert (lab[lab[nz]] == lab[nz]).all()
-    ci = np.flatnonzero(core)
-    assert (lab[ci] <= ci).all() and (lab[ci] >= 0).all()
-    # per sampled row: neighbours, their exact core flags, label rules
-    for i in rows[:4]:
-        nb = np.flatnonzero(c_oracle.row_neighbours(w.points, w.eps, int(i)))
-        nb_core = c_oracle.row_counts(w.points, w.eps, nb) >= w.minpts
-        np.testing.assert_array_equal(core[nb], nb_core)
-        core_nb = nb[nb_core]
-        if core[i]:
-            assert (lab[core_nb] == lab[i]).all()
-        elif core_nb.size:
-            assert lab[i] == lab[core_nb.min()]
-        else:
-            assert lab[i] == -1
-    assert n == len(lab)
+def golden(name: str) -> dict:
+    """The committed oracle digests of a full-size workload
+    (tests/golden/full_size/<name>.json, written by make_full_size.py)."""
+    with open(os.path.join(GOLDEN_DIR, "full_size", f"{name}.json")) as f:
+        return json.load(f)
+
+
+def golden_job(j: int) -> dict:
+    rec = golden("served_jobs")
+    return rec["records"][rec["jobs"].index(j)]
+
+
+def assert_golden(rec: dict, points, gpu, what: str = "") -> None:
+    """Every element of (labels, core, counts) equals the oracle's: the
+    SHA-256 of each whole array must match the digest the oracle's outputs
+    gave.  On a mismatch, the index blocks whose digests differ are named."""
+    assert mfs.sha(np.asarray(points, dtype="<f4")) == rec["points_sha256"], \
+        f"{what}: input points differ from those the digests were taken on"
+    lab, cor, cnt = mfs.canonical(*gpu[:3])
+    assert lab.shape[0] == rec["n"]
+    bad = []
+    for key, arr in (("counts", cnt), ("core", cor), ("labels", lab)):
+        if mfs.sha(arr) == rec[f"{key}_sha256"]:
+            continue
+        blocks = [b for b, (lo, hi) in enumerate(rec["blocks"])
+                  if mfs.sha(arr[lo:hi])[:16] != rec["block_sha256_16"][key][b]]
+        bad.append(f"{key}: {len(blocks)} of {len(rec['blocks'])} index blocks differ, first "
+                   f"{[tuple(rec['blocks'][b]) for b in blocks[:4]]}")
+    assert not bad, f"{what}: " + "; ".join(bad)
+    s = rec["summary"]
+    assert int(cor.sum()) == s["core_points"] and int((lab == -1).sum()) == s["noise"]

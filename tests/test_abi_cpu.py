@@ -36,7 +36,7 @@ def test_version_and_strerror():
 
 
 @pytest.mark.parametrize("kw", [
-    dict(n=0), dict(n=-5), dict(d=0), dict(d=1025), dict(eps=-1.0), dict(eps=float("nan")),
+    dict(n=0), dict(n=-5), dict(n=2**31 - 65), dict(n=2**31 - 255), dict(n=2**31), dict(d=0), dict(d=1025), dict(eps=-1.0), dict(eps=float("nan")),
     dict(eps=float("inf")), dict(minpts=0), dict(points=None), dict(labels=None),
     dict(core=None), dict(counts=None)])
 def test_invalid_arguments_rejected_before_any_device_work(kw):
@@ -50,6 +50,20 @@ def test_invalid_arguments_rejected_before_any_device_work(kw):
     rc = L.dbscan_fit(args["points"], args["n"], args["d"], args["eps"], args["minpts"],
                       args["labels"], args["core"], args["counts"], None)
     assert rc == _lib.DBSCAN_E_INVAL
+
+
+def test_largest_n_keeps_the_padded_count_in_int32():
+    """n is padded up to a multiple of 256 rows; the largest accepted n must
+    keep that padded count below 2^31."""
+    L = _lib.load()
+    out = ctypes.c_uint64()
+    o = _lib.make_opts("onthefly")
+    for n in (2**31 - 255, 2**31 - 65, 2**31 - 1):
+        assert L.dbscan_workspace_size(n, 2, ctypes.byref(o), ctypes.byref(out)) == \
+            _lib.DBSCAN_E_INVAL
+    assert L.dbscan_workspace_size(2**31 - 256, 2, ctypes.byref(o), ctypes.byref(out)) == \
+        _lib.DBSCAN_OK
+    assert (2**31 - 256) % 256 == 0
 
 
 def test_bad_options_rejected():

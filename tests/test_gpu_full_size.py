@@ -1,0 +1,94 @@
+"""GPU parity at full size, element by element.
+
+Every form of the path runs each full-size workload exactly as the benchmark
+does, and its counts, core flags and labels must equal the float64 oracle's
+everywhere (Section II's definitions): the comparison is against SHA-256
+digests of the whole arrays that ``tests/golden/make_full_size.py`` wrote from
+the C oracle alone (and of 64 index blocks, which name where a mismatch
+lies).  The launch shapes differ from those of the scaled tests -- row
+chunks, pair-list segments, the spatial order, the matrix-core item order
+-- which is why the full sizes are checked in full."""
+import functools
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_1506_02226_amd as pkg
+from paper_1506_02226_amd import workloads as wl
+from helpers import assert_golden, golden, golden_job
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=2)
+def _workload(name):
+    w = wl.by_name(name)
+    return w, torch.from_numpy(w.points).to("cuda:0")
+
+
+def _run(x, eps, minpts, **kw):
+    lab, core, cnt, st = pkg.fit(x, eps, minpts, stats=True, **kw)
+    torch.cuda.synchronize()
+    return lab.cpu().numpy(), core.cpu().numpy(), cnt.cpu().numpy(), st
+
+
+BLOBS2D_FORMS = [dict(adjacency=a, order=o, prune=p)
+                 for a in ("bitmask", "onthefly") for o in ("spatial", "input")
+                 for p in (False, True)]
+
+
+@pytest.mark.parametrize("form", BLOBS2D_FORMS, ids=lambda f: "-".join(
+    [f["adjacency"], f["order"]] + (["pruned"] if f["prune"] else [])))
+def test_blobs2d_200k(form):
+    w, x = _workload("blobs2d_200k")
+    out = _run(x, w.eps, w.minpts, **form)
+    st = out[3]
+    assert st["adjacency_used"] == form["adjacency"] and st["order_used"] == form["order"]
+    assert st["pruned"] == int(form["prune"])
+    assert_golden(golden("blobs2d_200k"), w.points, out, str(form))
+
+
+def test_blobs2d_200k_default_form():
+    """What the library picks by itself at this size (the benchmarked form)."""
+    w, x = _workload("blobs2d_200k")
+    out = _run(x, w.eps, w.minpts)
+    assert out[3]["adjacency_used"] == "bitmask" and out[3]["order_used"] == "spatial"
+    assert_golden(golden("blobs2d_200k"), w.points, out, "auto")
+
+
+ANISO_FORMS = [dict(order="spatial", prune=False), dict(order="input", prune=False),
+               dict(order="spatial", prune=True)]
+
+
+@pytest.mark.parametrize("form", ANISO_FORMS, ids=lambda f: f["order"] + (
+    "-pruned" if f["prune"] else ""))
+def test_aniso3d_2m(form):
+    w, x = _workload("aniso3d_2m")
+    out = _run(x, w.eps, w.minpts, **form)
+    st = out[3]
+    assert st["adjacency_used"] == "onthefly" and st["order_used"] == form["order"]
+    assert_golden(golden("aniso3d_2m"), w.points, out, str(form))
+
+
+@pytest.mark.parametrize("name", ["mix64d_300k", "mix64d_300k_q50"])
+@pytest.mark.parametrize("prec", ["fp16", "bf16", "fp32"])
+@pytest.mark.parametrize("order", ["spatial", "input"])
+def test_mix64d_300k(name, prec, order):
+    w, x = _workload(name)
+    out = _run(x, w.eps, w.minpts, precision=prec, order=order)
+    st = out[3]
+    assert st["precision_used"] == prec and st["order_used"] == order
+    assert st["filter_fallback"] == 0
+    assert_golden(golden(name), w.points, out, f"{prec} {order}")
+
+
+@pytest.mark.parametrize("j", range(32))
+def test_served_job_alone(j):
+    """The served workload's jobs 0-31, each run alone through dbscan_fit_ex
+    in the form the library picks."""
+    rec = golden_job(j)
+    w = wl.served_job(j)
+    out = _run(torch.from_numpy(w.points).to("cuda:0"), w.eps, w.minpts)
+    assert_golden(rec, w.points, out, f"job {j}")

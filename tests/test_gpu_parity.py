@@ -2,8 +2,8 @@
 
 Counts, core flags and labels must be bit-identical to the float64 oracle.
 Sizes stay where the oracle finishes in seconds but span several tiles and
-ragged tails; full-size workloads are checked on sampled rows (exact) and on
-invariants that hold at any size."""
+ragged tails; the full-size workloads are compared element by element in
+test_gpu_full_size.py."""
 import numpy as np
 import pytest
 
@@ -12,7 +12,6 @@ torch = pytest.importorskip("torch")
 import paper_1506_02226_amd as pkg
 from oracle import c_oracle, dbscan_oracle as orc
 from paper_1506_02226_amd import workloads as wl
-from helpers import sampled_checks
 
 pytestmark = pytest.mark.gpu
 
@@ -194,29 +193,6 @@ def test_scaled_recipes_full_parity(name, n):
         assert_same(run(w.points, w.eps, w.minpts, adjacency=mode), ref, f"{name} {mode}")
 
 
-def test_blobs2d_200k_full_size():
-    w = wl.blobs2d_200k(0)
-    gpu = run(w.points, w.eps, w.minpts, stats=True)
-    assert gpu[3]["adjacency_used"] == "bitmask"
-    rng = np.random.default_rng(0)
-    rows = np.sort(rng.choice(w.n, 64, replace=False))
-    rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:8]])
-    sampled_checks(w, gpu, rows)
-    other = run(w.points, w.eps, w.minpts, adjacency="onthefly")
-    for x, y in zip(gpu[:3], other):
-        np.testing.assert_array_equal(x, y)
-
-
-def test_aniso3d_2m_full_size():
-    w = wl.aniso3d_2m(0)
-    gpu = run(w.points, w.eps, w.minpts, stats=True)
-    assert gpu[3]["adjacency_used"] == "onthefly"
-    rng = np.random.default_rng(1)
-    rows = np.sort(rng.choice(w.n, 16, replace=False))
-    rows = np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]])
-    sampled_checks(w, gpu, rows)
-
-
 @pytest.mark.parametrize("cap", [1, 100, 0])
 def test_pair_list_overflow_falls_back(cap):
     """The on-the-fly form records neighbour pairs for the merge; when they do
@@ -327,27 +303,6 @@ def test_mix64d_scaled_parity(prec):
     w = wl.mix64d_300k(0, n=8000, eps_rule="q50")
     ref = c_oracle.dbscan(w.points, w.eps, w.minpts)
     assert_same(run(w.points, w.eps, w.minpts, precision=prec), ref, prec)
-
-
-def test_mix64d_full_size_all_forms():
-    """n=300,000, d=64: the FP16 and BF16 filters and the plain float32 form
-    agree on every output at the literal eps (almost all noise) and at the
-    median core distance; sampled rows are exact against the oracle."""
-    for rule in ("literal", "q50"):
-        w = wl.mix64d_300k(0, eps_rule=rule)
-        outs = {p: run(w.points, w.eps, w.minpts, precision=p, stats=True)
-                for p in ("fp16", "bf16", "fp32")}
-        for p in ("bf16", "fp32"):
-            for x, y in zip(outs["fp16"][:3], outs[p][:3]):
-                np.testing.assert_array_equal(x, y, err_msg=f"{rule} fp16 vs {p}")
-        assert outs["fp16"][3]["filter_fallback"] == 0 and outs["bf16"][3]["filter_fallback"] == 0
-        rng = np.random.default_rng(2)
-        rows = np.sort(rng.choice(w.n, 24, replace=False))
-        gpu = outs["fp16"]
-        assert (gpu[2] >= 1).all()
-        if rule == "q50":
-            assert 0 < gpu[1].sum() < w.n
-        sampled_checks(w, gpu, np.concatenate([rows, np.flatnonzero(~gpu[1])[:4]]))
 
 
 @pytest.mark.parametrize("prec", PRECS)

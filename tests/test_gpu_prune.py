@@ -12,7 +12,6 @@ torch = pytest.importorskip("torch")
 
 from oracle import c_oracle, dbscan_oracle as orc
 from paper_1506_02226_amd import workloads as wl
-from helpers import sampled_checks
 from test_gpu_parity import assert_same, run
 
 pytestmark = pytest.mark.gpu
@@ -81,18 +80,3 @@ def test_prune_scaled_recipes(name):
         assert_same(gpu, ref, f"{name} {mode}")
         # clustered data in spatial order: most tile pairs are far apart
         assert gpu[3]["sweep1_tests"] < 0.25 * w.n * w.n / 2
-
-
-@pytest.mark.parametrize("name", ["blobs2d_200k", "aniso3d_2m"])
-def test_prune_full_size(name):
-    """Full-size workloads: pruned outputs equal the unpruned ones and the
-    oracle on sampled rows."""
-    w = wl.by_name(name, 0)
-    gpu = run(w.points, w.eps, w.minpts, prune=True, stats=True)
-    assert gpu[3]["pruned"] == 1 and gpu[3]["order_used"] == "spatial"
-    full = run(w.points, w.eps, w.minpts)
-    for x, y in zip(gpu[:3], full[:3]):
-        np.testing.assert_array_equal(x, y)
-    rng = np.random.default_rng(5)
-    rows = np.sort(rng.choice(w.n, 16, replace=False))
-    sampled_checks(w, gpu, rows)

@@ -14,7 +14,7 @@ import fp64_order as fo
 from oracle import c_oracle, dbscan_oracle as orc
 
 
-@pytest.fixture(scope="module", params=[8, 16])
+@pytest.fixture(scope="module", params=[2, 3, 8, 16])
 def order_cases(request):
     return fo.cases(request.param)
 
@@ -25,7 +25,8 @@ def _pair(c):
 
 def test_cases_separate_every_variant(order_cases):
     seen = {(c["variant"], c["direction"]) for c in order_cases}
-    assert seen == {(v, dr) for v in fo.VARIANTS for dr in ("in", "out")}
+    assert seen == {(v, dr) for v in fo.variants_for(len(order_cases[0]["a"]))
+                    for dr in ("in", "out")}
     for c in order_cases:
         e2 = orc.eps_squared(c["eps"])
         assert (c["seq"] <= e2) == c["in"] and (c["alt"] <= e2) != c["in"]
@@ -88,4 +89,6 @@ def test_planted_order_mistakes_fail(order_cases, monkeypatch, variant, planted)
             continue
         adj = orc.neighbour_matrix(_pair(c), c["eps"])
         wrong += int(adj[0, 1] != c["in"])
+    if not any(c["variant"] == variant for c in order_cases):
+        pytest.skip(f"{variant} equals the sequential sum at this d")
     assert wrong == 2  # both directions flip
