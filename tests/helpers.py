@@ -16,7 +16,11 @@ import make_full_size as mfs  # noqa: E402  (digest layout shared with the write
 def golden(name: str) -> dict:
     """The committed oracle digests of a full-size workload
     (tests/golden/full_size/<name>.json, written by make_full_size.py)."""
-    with open(os.path.join(GOLDEN_DIR, "full_size", f"{name}.json")) as f:
+    path = os.path.join(GOLDEN_DIR, "full_size", f"{name}.json")
+    if not os.path.exists(path):
+        import pytest
+        pytest.skip(f"no oracle digests for {name} (tests/golden/make_full_size.py {name})")
+    with open(path) as f:
         return json.load(f)
 
 
