@@ -64,6 +64,9 @@ extern "C" {
  * (the padded row count) is still an int32 index. */
 #define DBSCAN_MAX_N 2147483392LL
 
+/* Device array behind dbscan_fit_noalloc, per GPU (64 MiB). */
+#define DBSCAN_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
 /* How the neighbour relation is kept between step 2 and step 3. */
 #define DBSCAN_ADJ_AUTO 0     /* bitmask when it fits the limit, else on the fly */
 #define DBSCAN_ADJ_BITMASK 1  /* one bit per ordered pair, kept in device memory */
@@ -186,6 +189,26 @@ int dbscan_fit(const float *points, int64_t n, int32_t d, double eps, int32_t mi
 int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
                   int32_t *labels, uint8_t *core, int32_t *counts, void *stream,
                   const dbscan_opts *opts, dbscan_stats *stats);
+
+/*
+ * dbscan_fit_noalloc -- dbscan_fit for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments, results and asynchrony as dbscan_fit;
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Its workspace is a library array of DBSCAN_NOALLOC_SCRATCH_BYTES
+ * in device memory, one per GPU, held from the library's load until the
+ * process ends.  The default plan is used when its workspace fits; otherwise
+ * the on-the-fly form runs with pair and band lists sized to the array (a
+ * full pair list makes step 3 repeat the epsilon tests; results are the
+ * same).  DBSCAN_E_NOMEM when even that does not fit: n above 1,274,880 at
+ * d = 3, 388,608 at d = 16, 120,320 at d = 64.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU (different streams, or
+ * different host threads without ordering) race and must be serialized by
+ * the caller.  The array keeps the last call's contents; each call
+ * initialises everything it reads.
+ */
+int dbscan_fit_noalloc(const float *points, int64_t n, int32_t d, double eps, int32_t minpts,
+                       int32_t *labels, uint8_t *core, int32_t *counts, void *stream);
 
 /*
  * dbscan_workspace_size -- bytes of device scratch dbscan_fit_ex needs for

@@ -32,6 +32,7 @@ ORDER_NAMES = {v: k for k, v in ORDER.items()}
 EXPORTS = (
     "dbscan_fit",
     "dbscan_fit_ex",
+    "dbscan_fit_noalloc",
     "dbscan_workspace_size",
     "dbscan_strerror",
     "dbscan_version",
@@ -173,6 +174,8 @@ def load(path: str | None = None):
     L.dbscan_fit_ex.argtypes = [vp, i64, i32, dbl, i32, vp, vp, vp, vp,
                                 ctypes.POINTER(Opts), ctypes.POINTER(Stats)]
     L.dbscan_fit_ex.restype = ctypes.c_int
+    L.dbscan_fit_noalloc.argtypes = [vp, i64, i32, dbl, i32, vp, vp, vp, vp]
+    L.dbscan_fit_noalloc.restype = ctypes.c_int
     L.dbscan_workspace_size.argtypes = [i64, i32, ctypes.POINTER(Opts),
                                         ctypes.POINTER(ctypes.c_uint64)]
     L.dbscan_workspace_size.restype = ctypes.c_int
