@@ -237,19 +237,30 @@ def serve_bench(args) -> int:
         return {"span_s": span, "jobs_per_s": len(jobs) / span, "lat_ms": lat, "stats": stats,
                 "failed": bad, "fallback": sum(s["fallback"] for s in sts)}
 
+    def sequential():
+        """The same jobs one by one through dbscan_fit (default options),
+        enqueued back to back on one stream: the plain GPU form's rate."""
+        seq = [tuple(torch.empty_like(t) for t in o) for o in outs]
+        for k in range(min(8, len(jobs))):  # warm-up
+            pkg.fit(xs[k], jobs[k][1], jobs[k][2], out=seq[k])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k, (x, (_, eps, mpts)) in enumerate(zip(xs, jobs)):
+            pkg.fit(x, eps, mpts, out=seq[k])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, seq
+
+    seq_s, seq_outs = sequential()
     closed = run(None)
     rate = args.rate_frac * closed["jobs_per_s"]
     arrivals = workloads.served_arrivals(len(jobs), rate, seed=0)
     opened = run(arrivals)
-    # each result equals the same job run alone
-    rng = np.random.default_rng(0)
+    # every served result equals the same job run alone
     mismatches = 0
-    check = rng.choice(len(jobs), size=min(24, len(jobs)), replace=False)
-    for k in check:
-        _, eps, mpts = jobs[k]
-        alone = pkg.fit(xs[k], eps, mpts)
-        for a, b in zip(outs[k], alone):
+    for k in range(len(jobs)):
+        for a, b in zip(outs[k], seq_outs[k]):
             mismatches += int(not torch.equal(a, b))
+    del seq_outs
     lat = opened["lat_ms"]
     rec = {
         "metric": "served jobs: p50/p99 latency, jobs/s",
@@ -274,10 +285,95 @@ def serve_bench(args) -> int:
         "failed": opened["failed"] + closed["failed"],
         "standalone_fallbacks": opened["fallback"],
         "alone_vs_mix_mismatches": mismatches,
+        "alone_vs_mix_checked_jobs": len(jobs),
+        "sequential": {"jobs_per_s": round(len(jobs) / seq_s, 2),
+                       "gpairs_per_s": round(pairs_tot / seq_s / 1e9, 3),
+                       "seconds": round(seq_s, 3),
+                       "what": "the same jobs one by one through dbscan_fit on one stream"},
+        "served_speedup_vs_sequential": round(closed["jobs_per_s"] / (len(jobs) / seq_s), 3),
         "generation_s": round(t_gen, 1),
     }
     print(json.dumps(rec), flush=True)
     return 0
+
+
+# The paper's step times at N = 23,040 (Tables III and IV, Tesla K10 GK104),
+# quoted beside the ablation as context.
+PAPER_TABLES_MS = {"dist_baseline": 1482.24, "dist_coalesced": 48.128, "dist_shared": 23.867,
+                   "dist_unrolled": 5.3037, "cluster_from_dist": 44.848,
+                   "cluster_fused": 25.336, "cluster_hoisted": 12.502,
+                   "merge_targets": 22.48}
+
+
+def paper_ablation(args) -> int:
+    """The paper's own design (include/dbscan_paper.h) step by step on the
+    3-D workload at one of its sizes, beside the main path's steps on the
+    same points: a Table III / Table IV style breakdown.  Every product is
+    checked against the main path's outputs (counts, core flags, labels)."""
+    import torch
+    import paper_1506_02226_amd as pkg
+    from paper_1506_02226_amd import paper, workloads
+
+    w = workloads.paper3d(0, args.ablation_n)
+    n = w.n
+    x = torch.from_numpy(w.points).to("cuda:0")
+    ref = [t.cpu() for t in pkg.fit(x, w.eps, w.minpts)]
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    rows = {}
+    dist = torch.empty((n, n), dtype=torch.float32, device=x.device)
+    for k in paper.DIST_KERNELS:
+        ms = timed(lambda: paper.distance(x, k, out=dist), 1 if k == "baseline" else 3)
+        rows[f"dist_{k}"] = {"ms": round(ms, 4),
+                             "write_gb_s": round(4.0 * n * n / (ms * 1e-3) / 1e9, 1)}
+    out = (torch.empty((n, n), dtype=torch.uint8, device=x.device),
+           torch.empty(n, dtype=torch.uint8, device=x.device),
+           torch.empty(n, dtype=torch.int32, device=x.device))
+    ok = True
+    for k in paper.CLUSTER_KERNELS:
+        d_in = dist if k == "from_dist" else None
+        ms = timed(lambda: paper.cluster(x, w.eps, w.minpts, k, dist=d_in, out=out), 3)
+        _, _, _, rech = paper.cluster(x, w.eps, w.minpts, k, dist=d_in, out=out, rechecked=True)
+        ok &= torch.equal(out[2].cpu(), ref[2]) and torch.equal(out[1].cpu(), ref[1])
+        rows[f"cluster_{k}"] = {"ms": round(ms, 4), "pairs_rechecked_fp64": rech}
+    for k in paper.MERGE_KERNELS:
+        if k == "warshall" and n > args.warshall_max_n:
+            rows["merge_warshall"] = {"skipped": f"n > {args.warshall_max_n} (n launches)"}
+            continue
+        paper.cluster(x, w.eps, w.minpts, "hoisted", out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lab, launches = paper.merge(out[0], out[1], k)
+        ms = (time.perf_counter() - t0) * 1e3
+        ok &= torch.equal(lab.cpu(), ref[0])
+        rows[f"merge_{k}"] = {"ms": round(ms, 3), "launches": launches}
+    del dist, out
+    torch.cuda.empty_cache()
+    _, _, _, st = pkg.fit(x, w.eps, w.minpts, stats=True)
+    for _ in range(3):
+        _, _, _, st = pkg.fit(x, w.eps, w.minpts, stats=True)
+    main = {"step1_ms": round(st["ms_step1"], 4), "step2_ms": round(st["ms_step2"], 4),
+            "step3_ms": round(st["ms_step3"], 4), "total_ms": round(st["ms_total"], 4),
+            "adjacency": st["adjacency_used"], "order": st["order_used"]}
+    rec = {"metric": "paper ablation: step times (ms)", "unit": "ms", "n_gpus": 1,
+           "data": "synthetic", "dtype": "f32",
+           "config": {"workload": "paper3d", "n": n, "d": 3, "eps": w.eps, "minpts": w.minpts},
+           "paper_design": rows, "main_path": main, "outputs_equal_main_path": bool(ok),
+           "paper_tables_ms_n23040_k10": PAPER_TABLES_MS}
+    print(json.dumps(rec), flush=True)
+    return 0 if ok else 1
 
 
 def main(argv=None) -> int:
@@ -304,6 +400,10 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for profiles)")
     ap.add_argument("--serve", action="store_true", help="served form (continuous batching)")
+    ap.add_argument("--paper-ablation", action="store_true",
+                    help="the paper's own kernels step by step (Tables III-IV) beside the main path")
+    ap.add_argument("--ablation-n", type=int, default=23_040)
+    ap.add_argument("--warshall-max-n", type=int, default=23_040)
     ap.add_argument("--jobs", type=int, default=5000)
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--rate-frac", type=float, default=0.7)
@@ -318,6 +418,8 @@ def main(argv=None) -> int:
 
     if args.serve:
         return serve_bench(args)
+    if args.paper_ablation:
+        return paper_ablation(args)
 
     import torch
     import paper_1506_02226_amd as pkg

@@ -28,7 +28,7 @@ ADJ_NAMES = {v: k for k, v in ADJ.items()}
 PREC_NAMES = {v: k for k, v in PREC.items()}
 ORDER_NAMES = {v: k for k, v in ORDER.items()}
 
-# Every symbol include/dbscan.h declares.
+# Every symbol include/dbscan.h and include/dbscan_paper.h declare.
 EXPORTS = (
     "dbscan_fit",
     "dbscan_fit_ex",
@@ -43,6 +43,9 @@ EXPORTS = (
     "dbscan_batch_wait",
     "dbscan_server_get_stats",
     "dbscan_server_destroy",
+    "dbscan_paper_distance",
+    "dbscan_paper_cluster",
+    "dbscan_paper_merge",
 )
 
 JOB_QUEUED, JOB_RUNNING, JOB_DONE, JOB_FAILED = 0, 1, 2, 3
@@ -199,6 +202,14 @@ def load(path: str | None = None):
     L.dbscan_server_get_stats.restype = ctypes.c_int
     L.dbscan_server_destroy.argtypes = [sp]
     L.dbscan_server_destroy.restype = ctypes.c_int
+    u8p = ctypes.c_void_p
+    L.dbscan_paper_distance.argtypes = [vp, i64, i32, i32, vp, vp]
+    L.dbscan_paper_distance.restype = ctypes.c_int
+    L.dbscan_paper_cluster.argtypes = [vp, vp, i64, i32, dbl, i32, i32, vp, vp, vp,
+                                       ctypes.POINTER(ctypes.c_uint64), vp]
+    L.dbscan_paper_cluster.restype = ctypes.c_int
+    L.dbscan_paper_merge.argtypes = [u8p, vp, i64, i32, vp, vp, ctypes.POINTER(ctypes.c_int64), vp]
+    L.dbscan_paper_merge.restype = ctypes.c_int
     if path is None:
         _lib = L
     return L

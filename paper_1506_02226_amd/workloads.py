@@ -147,6 +147,26 @@ def aniso3d_2m(seed: int = 0, n: int = 2_000_000) -> Workload:
     return Workload("aniso3d_2m", pts, 0.4, 20, {"seed": seed, "blobs": k, "noise": 0.05})
 
 
+def paper3d(seed: int = 0, n: int = 23_040) -> Workload:
+    """3-D points at the paper's own sizes (N = 5,061 / 23,040 / 60,032 in
+    Tables I and III-V; its dataset is not published): 20 anisotropic
+    Gaussian blobs (covariance Q diag(lambda) Q^T, lambda ~ U[0.1, 1]) with
+    centres in [0, 60]^3, plus 5% uniform noise; eps = 0.4, MinPts = 20."""
+    rng = np.random.default_rng(seed)
+    d, k, box = 3, 20, 60.0
+    n_noise = int(round(0.05 * n))
+    centres = rng.uniform(0.0, box, size=(k, d))
+    rots = [_haar_rotation(rng, d) for _ in range(k)]
+    lams = rng.uniform(0.1, 1.0, size=(k, d))
+    blob_pts = []
+    for b, m in enumerate(blob_sizes(n - n_noise, k)):
+        z = rng.standard_normal((m, d)) * np.sqrt(lams[b])[None, :]
+        blob_pts.append(centres[b] + z @ rots[b].T)
+    noise = rng.uniform(0.0, box, size=(n_noise, d))
+    pts = _finish(rng, blob_pts, noise)
+    return Workload("paper3d", pts, 0.4, 20, {"seed": seed, "blobs": k, "noise": 0.05})
+
+
 def mixture_blobs(
     rng: np.random.Generator, n: int, d: int, k: int, noise_frac: float, radius: float = 10.0
 ) -> np.ndarray:
@@ -237,6 +257,7 @@ WORKLOADS = {
     "aniso3d_2m": aniso3d_2m,
     "mix64d_300k": mix64d_300k,
     "mix64d_300k_q50": lambda seed=0, n=300_000: mix64d_300k(seed, n, "q50"),
+    "paper3d": paper3d,
 }
 
 

@@ -15,9 +15,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "dbscan.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return set(re.findall(r"^\s*(?:int|const char \*)\s*(dbscan_\w+)\s*\(", text, re.M))
+    names = set()
+    for h in ("dbscan.h", "dbscan_paper.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"^\s*(?:int|const char \*)\s*(dbscan_\w+)\s*\(", text, re.M))
+    return names
 
 
 def test_exports_every_declared_symbol():
@@ -64,6 +67,29 @@ def test_largest_n_keeps_the_padded_count_in_int32():
     assert L.dbscan_workspace_size(2**31 - 256, 2, ctypes.byref(o), ctypes.byref(out)) == \
         _lib.DBSCAN_OK
     assert (2**31 - 256) % 256 == 0
+
+
+def test_paper_entry_points_reject_bad_arguments():
+    """The ablation entry points check their arguments on the host."""
+    L = _lib.load()
+    P = 0x1000
+    assert L.dbscan_paper_distance(P, 100, 3, 0, P, None) == _lib.DBSCAN_E_INVAL   # kernel
+    assert L.dbscan_paper_distance(P, 100, 3, 5, P, None) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_distance(P, 100, 5, 4, P, None) == _lib.DBSCAN_E_INVAL   # d > 4
+    assert L.dbscan_paper_distance(P, 0, 3, 4, P, None) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_distance(P, 131073, 3, 4, P, None) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_distance(None, 10, 3, 4, P, None) == _lib.DBSCAN_E_INVAL
+    # kernel 5 needs the distance matrix, 6 and 7 must not get one
+    assert L.dbscan_paper_cluster(P, None, 10, 3, 1.0, 2, 5, P, P, P, None, None) == \
+        _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_cluster(P, P, 10, 3, 1.0, 2, 6, P, P, P, None, None) == \
+        _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_cluster(P, None, 10, 3, -1.0, 2, 6, P, P, P, None, None) == \
+        _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_cluster(P, None, 10, 3, 1.0, 0, 7, P, P, P, None, None) == \
+        _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_merge(P, P, 10, 7, P, None, None, None) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_paper_merge(None, P, 10, 8, P, None, None, None) == _lib.DBSCAN_E_INVAL
 
 
 def test_bad_options_rejected():
