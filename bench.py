@@ -237,20 +237,33 @@ def serve_bench(args) -> int:
         return {"span_s": span, "jobs_per_s": len(jobs) / span, "lat_ms": lat, "stats": stats,
                 "failed": bad, "fallback": sum(s["fallback"] for s in sts)}
 
-    def sequential():
-        """The same jobs one by one through dbscan_fit (default options),
-        enqueued back to back on one stream: the plain GPU form's rate."""
+    def sequential(pruned):
+        """The same jobs one by one through dbscan_fit, enqueued back to back
+        on one stream: the plain GPU form's rate, with the default options,
+        or (pruned) with the options the server's workers use (spatial order
+        and tile pruning for d <= 4)."""
         seq = [tuple(torch.empty_like(t) for t in o) for o in outs]
+
+        def one(k):
+            x = xs[k]
+            kw = dict(order="spatial", prune=True) if pruned and x.shape[1] <= 4 else {}
+            pkg.fit(x, jobs[k][1], jobs[k][2], out=seq[k], **kw)
+
         for k in range(min(8, len(jobs))):  # warm-up
-            pkg.fit(xs[k], jobs[k][1], jobs[k][2], out=seq[k])
+            one(k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k, (x, (_, eps, mpts)) in enumerate(zip(xs, jobs)):
-            pkg.fit(x, eps, mpts, out=seq[k])
+        for k in range(len(jobs)):
+            one(k)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, seq
 
-    seq_s, seq_outs = sequential()
+    seqp_s, seqp_outs = sequential(True)
+    seq_s, seq_outs = sequential(False)
+    for k in range(len(jobs)):
+        for a, b in zip(seqp_outs[k], seq_outs[k]):
+            assert torch.equal(a, b), f"pruned and unpruned outputs differ on job {k}"
+    del seqp_outs
     closed = run(None)
     rate = args.rate_frac * closed["jobs_per_s"]
     arrivals = workloads.served_arrivals(len(jobs), rate, seed=0)
@@ -290,7 +303,14 @@ def serve_bench(args) -> int:
                        "gpairs_per_s": round(pairs_tot / seq_s / 1e9, 3),
                        "seconds": round(seq_s, 3),
                        "what": "the same jobs one by one through dbscan_fit on one stream"},
+        "sequential_pruned": {"jobs_per_s": round(len(jobs) / seqp_s, 2),
+                              "gpairs_per_s": round(pairs_tot / seqp_s / 1e9, 3),
+                              "seconds": round(seqp_s, 3),
+                              "what": "the same jobs one by one through dbscan_fit with the "
+                                      "workers' options (spatial order, pruning for d <= 4)"},
         "served_speedup_vs_sequential": round(closed["jobs_per_s"] / (len(jobs) / seq_s), 3),
+        "served_speedup_vs_sequential_pruned": round(
+            closed["jobs_per_s"] / (len(jobs) / seqp_s), 3),
         "generation_s": round(t_gen, 1),
     }
     print(json.dumps(rec), flush=True)

@@ -230,14 +230,22 @@ int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_
 int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi);
 
 /* ------------------------------------------------------------------ serving
- * A server keeps a device job table and runs the jobs of many callers in one
- * persistent kernel, relaunched every epoch (a time slice of ~2 ms):
- * submitted jobs wait in a FIFO until a slot is free and their device-memory
- * footprint (the dbscan_fit workspace of the job) fits in the server's arena;
- * admitted jobs' block-sized tasks interleave on the device, and jobs that
- * arrive while others run are admitted at the next epoch.  Each job's outputs
- * equal those of dbscan_fit on the same inputs.  All entry points are
- * thread-safe.
+ * A server runs the jobs of many callers on one GPU.  Small jobs (n up to
+ * 16,384; float32 for d <= 4, FP16 matrix cores for 16 <= d <= 76) share one
+ * persistent kernel, relaunched every epoch (a time slice of ~2 ms): they
+ * wait in a FIFO until a slot is free and their device-memory footprint fits
+ * in the server's arena, their block-sized tasks interleave on the device,
+ * and jobs that arrive while others run are admitted at the next epoch.
+ * Every other job (larger n, other d, a precision the loop does not run, or
+ * a small job whose lists overflowed) runs the dbscan_fit_ex path on one of
+ * six worker streams (float32 jobs with d <= 4 in the spatial order with
+ * tile pruning), with its workspace taken from the same arena, so its
+ * kernels overlap with the epochs and with the other workers' jobs.  Each
+ * job's outputs equal those of dbscan_fit on the same inputs.  All entry
+ * points are thread-safe.  The caller's work that produces a job's points
+ * must be complete before dbscan_batch_submit (the server reads them on its
+ * own streams, unordered with the caller's), and the output buffers must not
+ * be used by other work until the job is finished.
  */
 typedef struct dbscan_server dbscan_server;
 
@@ -256,6 +264,8 @@ typedef struct dbscan_job {
   uint8_t *core;
   int32_t *counts;
   uint64_t tag;          /* caller's value, returned in the status */
+  int32_t precision;     /* DBSCAN_PREC_* as in dbscan_opts (AUTO = dbscan_fit's choice) */
+  int32_t reserved;      /* 0 */
 } dbscan_job;
 
 typedef struct dbscan_job_status {
@@ -266,7 +276,7 @@ typedef struct dbscan_job_status {
   int64_t t_done_ns;     /* completion (device clock mapped to the host clock) */
   uint64_t footprint;    /* device bytes held while running */
   uint64_t tag;
-  int32_t fallback;      /* 1 if the job ran through the dbscan_fit path */
+  int32_t fallback;      /* 1 if the job ran through the dbscan_fit_ex path on a worker */
   int32_t reserved;
 } dbscan_job_status;
 
@@ -292,19 +302,23 @@ int dbscan_server_create(int device, uint64_t hbm_budget_bytes, int32_t max_slot
 /*
  * dbscan_batch_submit -- queue one job (HOST struct, DEVICE buffers that must
  * stay valid until the job is finished).  *job_id (HOST) receives its id.
- * DBSCAN_E_INVAL for bad arguments, DBSCAN_E_NOMEM if the job's footprint
- * exceeds the whole arena, DBSCAN_E_AGAIN if the queue is full.
+ * DBSCAN_E_INVAL for bad arguments, DBSCAN_E_UNSUPPORTED for a precision the
+ * job's d does not allow, DBSCAN_E_NOMEM if the job's footprint exceeds the
+ * whole arena, DBSCAN_E_AGAIN if the queue is full.
  */
 int dbscan_batch_submit(dbscan_server *s, const dbscan_job *job, uint64_t *job_id);
 
 /*
  * dbscan_batch_poll -- status of a job (HOST out).  Returns DBSCAN_OK once the
  * job is finished (state DONE or FAILED), DBSCAN_PENDING before, and
- * DBSCAN_E_INVAL for an unknown id.
+ * DBSCAN_E_INVAL for an unknown id.  A finished job's status is returned
+ * once: the server then forgets the job (a later poll gives DBSCAN_E_INVAL),
+ * so a long-lived server holds only unfinished and unread jobs.
  */
 int dbscan_batch_poll(dbscan_server *s, uint64_t job_id, dbscan_job_status *st);
 
-/* dbscan_batch_wait -- dbscan_batch_poll that blocks up to timeout_ns. */
+/* dbscan_batch_wait -- dbscan_batch_poll that blocks up to timeout_ns (the
+ * finished status is likewise returned once). */
 int dbscan_batch_wait(dbscan_server *s, uint64_t job_id, int64_t timeout_ns,
                       dbscan_job_status *st);
 

@@ -106,10 +106,11 @@ class Server:
 
     ``submit`` queues a job on device tensors and returns its id; ``poll`` /
     ``wait`` return the status dict once the job is finished (None while it
-    is pending).  Jobs are admitted by device-memory footprint and run
-    together in the server's persistent kernel.  The caller keeps the input
-    and output tensors alive until the job is finished (``submit`` also keeps
-    a reference)."""
+    is pending; a finished status is returned once).  Jobs are admitted by
+    device-memory footprint: small ones run together in the server's
+    persistent kernel, the others on its worker streams beside it.  The
+    caller keeps the input and output tensors alive until the job is
+    finished (``submit`` also keeps a reference)."""
 
     def __init__(self, device: int = 0, hbm_budget: int = 0, max_slots: int = 256):
         self._L = _lib.load()
@@ -121,7 +122,8 @@ class Server:
         self._h = h
         self._keep = {}
 
-    def submit(self, points, eps: float, minpts: int, out=None, tag: int = 0) -> int:
+    def submit(self, points, eps: float, minpts: int, out=None, tag: int = 0,
+               precision: str = "auto") -> int:
         import torch
         x = _check_points(points)
         n, d = int(x.shape[0]), int(x.shape[1])
@@ -130,8 +132,11 @@ class Server:
                    torch.empty(n, dtype=torch.uint8, device=x.device),
                    torch.empty(n, dtype=torch.int32, device=x.device))
         labels, core, counts = out
+        # the server reads the points on its own streams: the work that made
+        # them (and any copy `_check_points` queued) must be complete
+        torch.cuda.current_stream(x.device).synchronize()
         job = _lib.Job(x.data_ptr(), n, d, int(minpts), float(eps), labels.data_ptr(),
-                       core.data_ptr(), counts.data_ptr(), int(tag))
+                       core.data_ptr(), counts.data_ptr(), int(tag), _lib.PREC[precision], 0)
         jid = ctypes.c_uint64()
         rc = self._L.dbscan_batch_submit(self._h, ctypes.byref(job), ctypes.byref(jid))
         if rc != _lib.DBSCAN_OK:

@@ -110,6 +110,8 @@ class Job(ctypes.Structure):
         ("core", ctypes.c_void_p),
         ("counts", ctypes.c_void_p),
         ("tag", ctypes.c_uint64),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

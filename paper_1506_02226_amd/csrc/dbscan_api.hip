@@ -105,7 +105,7 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     off += (uint64_t)round_up((int64_t)bytes, 256);
     return at;
   };
-  L->off_state = take(sizeof(dbk::DevState));
+  L->off_state = take(sizeof(dbk::DevState));  // first: the server reads its status word
   L->off_soa = take((uint64_t)L->d_pad * L->n_pad * 4);
   L->off_parent = take((uint64_t)L->n_pad * 4);
   L->off_jstar = take((uint64_t)L->n_pad * 4);

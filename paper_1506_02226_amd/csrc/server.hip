@@ -1,19 +1,30 @@
 // Served form, host side: admission by device-memory footprint, the job
-// table, and the loop that relaunches the persistent epoch kernel.
+// table, the loop that relaunches the persistent epoch kernel, and the
+// workers that run larger jobs through the standalone path.
 //
-//  * dbscan_batch_submit validates a job, computes its footprint (the same
-//    workspace sections as dbscan_fit: staged coordinates or FP16 copies,
-//    union-find, core bits, pair list, band list) and queues it (FIFO).
-//  * A server thread admits queued jobs while a slot is free and the
-//    footprint fits in the device-memory arena (first fit), writes their
-//    descriptors to the device job table, and launches one epoch of the
-//    persistent kernel (a time slice, 2 ms by default) over all admitted
-//    jobs.  After the epoch it reads the scheduling table back, releases
-//    finished jobs and admits more, so jobs that arrive while others run
-//    join at the next epoch boundary and overlap with them on the device.
-//  * Jobs the persistent loop does not cover (5 <= d <= 15, d > 76, BF16) or
-//    whose pair/band lists overflowed are run with dbscan_fit_ex between
-//    epochs; their results are the same.
+//  * dbscan_batch_submit validates a job, picks its route and footprint and
+//    queues it (FIFO per route):
+//      - the persistent loop takes small jobs (n <= loop_max_n, default
+//        16,384) of the forms it covers (float32 for d <= 4, FP16 matrix
+//        cores for 16 <= d <= 76): their footprint is the served sections
+//        (staged coordinates or FP16 copies, union-find, core bits, pair
+//        list, band list);
+//      - every other job runs dbscan_fit_ex on a worker's stream, with its
+//        workspace (dbscan_workspace_size for the job's precision) taken
+//        from the same arena, so admission bounds it too.
+//  * The loop thread admits queued small jobs while a slot is free and the
+//    footprint fits (first fit), writes their descriptors to the device job
+//    table, and launches one epoch of the persistent kernel (a time slice,
+//    2 ms by default) over all admitted jobs.  After the epoch it reads the
+//    scheduling table back, releases finished jobs and admits more, so jobs
+//    that arrive while others run join at the next epoch boundary and
+//    overlap with them on the device.  A small job whose pair or band list
+//    overflowed, or whose inputs left the FP16 range, moves to the front of
+//    the workers' queue (same results).
+//  * Six workers, each with its own stream, admit the larger jobs as
+//    arena memory frees up; their kernels overlap with the epochs and with
+//    each other on the device.  Float32 jobs with d <= 4 run there in the
+//    spatial order with tile pruning.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -45,6 +56,9 @@ inline uint64_t round_up(uint64_t v, uint64_t m) { return (v + m - 1) / m * m; }
 constexpr uint64_t kServePairsPerPoint = 128;  // as dbscan_fit's default
 constexpr uint64_t kServeBandPerPoint = 64;
 constexpr int kMaxQueue = 1 << 20;
+constexpr int kWorkers = 6;                    // streams for jobs outside the loop (default)
+constexpr int kMaxWorkers = 8;
+constexpr int64_t kLoopMaxN = 16384;           // largest job the loop takes by default
 
 // First-fit allocator over [0, size) in 256-byte units.
 class Arena {
@@ -97,11 +111,17 @@ struct ServeLayout {
   int64_t pair_cap = 0, band_cap = 0;
 };
 
-ServeLayout serve_layout(const dbscan_job &j) {
+ServeLayout serve_layout(const dbscan_job &j, int64_t loop_max_n) {
   ServeLayout L;
   const int d = j.d;
-  L.prec = (d >= 16 && d <= 76) ? DBSCAN_PREC_FP16 : DBSCAN_PREC_FP32;
-  L.persistent = dbk::serve_supports(d, L.prec == DBSCAN_PREC_FP16 ? dbk::kPrecFp16 : 1);
+  const int req = j.precision;
+  L.prec = (d >= 16 && d <= 76 && (req == DBSCAN_PREC_AUTO || req == DBSCAN_PREC_FP16))
+               ? DBSCAN_PREC_FP16
+               : DBSCAN_PREC_FP32;
+  const bool prec_ok = req == DBSCAN_PREC_AUTO || req == L.prec;
+  L.persistent = prec_ok && j.n <= loop_max_n &&
+                 dbk::serve_supports(d, L.prec == DBSCAN_PREC_FP16 ? dbk::kPrecFp16 : 1);
+  if (!L.persistent) return L;
   L.n_pad = (int)round_up((uint64_t)j.n, 256);
   L.d_pad = d;
   uint64_t off = 0;
@@ -139,10 +159,35 @@ void serve_band(double eps2, int32_t d, float *lo, float *hi) {
   dbscan_fp32_band(eps2, d, lo, hi);
 }
 
+// Options of a job run through dbscan_fit_ex on a worker: the job's
+// precision and, for float32 jobs with d <= 4, the spatial order with tile
+// pruning (same results, far fewer pair tests on clustered data).
+dbscan_opts direct_opts(const dbscan_job &j, bool prune) {
+  dbscan_opts o{};
+  o.precision = j.precision;
+  const bool fp32 = j.precision == DBSCAN_PREC_FP32 ||
+                    (j.precision == DBSCAN_PREC_AUTO && (j.d <= 4 || j.d > 76 || j.d < 16));
+  if (prune && j.d <= 4 && fp32) {
+    o.order = DBSCAN_ORDER_SPATIAL;
+    o.prune = 1;
+  }
+  return o;
+}
+
+uint64_t direct_bytes(const dbscan_job &j, bool prune, int *rc) {
+  const dbscan_opts o = direct_opts(j, prune);
+  uint64_t b = 0;
+  *rc = dbscan_workspace_size(j.n, j.d, &o, &b);
+  return b;
+}
+
 struct Record {
   dbscan_job job{};
   dbscan_job_status status{};
   ServeLayout layout;
+  bool direct = false;     // runs through dbscan_fit_ex on a worker
+  uint64_t need = 0;       // arena bytes while running
+  uint64_t held = 0;       // arena bytes held now
   uint64_t arena_off = 0;
   int slot = -1;
 };
@@ -165,12 +210,20 @@ struct dbscan_server {
   std::vector<uint64_t> slot_job;  // job id per slot (0 = free)
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<uint64_t> pending;
+  std::deque<uint64_t> pending;         // jobs for the persistent loop
+  std::deque<uint64_t> direct_pending;  // jobs for the workers
   std::unordered_map<uint64_t, Record> records;
   uint64_t next_id = 1;
   bool stopping = false;
+  bool loop_done = false;
   int error = DBSCAN_OK;
-  std::thread worker;
+  int64_t loop_max_n = kLoopMaxN;
+  int nworkers = kWorkers;
+  bool prune = true;
+  int direct_running = 0;
+  std::thread worker;                   // the loop thread
+  std::vector<std::thread> workers;
+  std::vector<hipStream_t> wstreams;
   // clock calibration: host ns = host0 + (ticks - dev0) * ns_per_tick
   int64_t host0 = 0;
   long long dev0 = 0;
@@ -184,9 +237,9 @@ struct dbscan_server {
     return dev0 + (long long)((double)(ns - host0) / ns_per_tick);
   }
   void loop();
+  void work(int w);
   bool admit_locked(std::vector<int> &fresh);
   void finish_locked(uint64_t id, int32_t state, int32_t error, int64_t t_done, int fallback);
-  void run_standalone(uint64_t id);
 };
 
 void dbscan_server::finish_locked(uint64_t id, int32_t state, int32_t err, int64_t t_done,
@@ -199,26 +252,84 @@ void dbscan_server::finish_locked(uint64_t id, int32_t state, int32_t err, int64
   if (r.slot >= 0) {
     slot_job[r.slot] = 0;
     r.slot = -1;
-    arena->release(r.arena_off, r.layout.total);
+  }
+  if (r.held) {
+    arena->release(r.arena_off, r.held);
+    r.held = 0;
   }
   stats.jobs_done += 1;
   stats.points_done += r.job.n;
   stats.pairs_done += (double)r.job.n * (double)r.job.n;
 }
 
-void dbscan_server::run_standalone(uint64_t id) {
-  dbscan_job j;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    j = records[id].job;
+// A worker: admits the oldest job of the workers' queue once its workspace
+// fits in the arena and runs it through dbscan_fit_ex on the worker's own
+// stream (the call waits for that stream, so the device time of one job
+// overlaps with the other workers' jobs and with the loop's epochs).
+void dbscan_server::work(int w) {
+  if (hipSetDevice(device) != hipSuccess) return;
+  const hipStream_t ws = wstreams[w];
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    uint64_t id = 0, off = 0;
+    if (!direct_pending.empty() && error == DBSCAN_OK) {
+      Record &r = records[direct_pending.front()];
+      if (arena->alloc(r.need, &off)) {
+        id = direct_pending.front();
+        direct_pending.pop_front();
+        r.arena_off = off;
+        r.held = r.need;
+        r.status.state = DBSCAN_JOB_RUNNING;
+        if (!r.status.t_admit_ns) r.status.t_admit_ns = now_ns();
+        r.status.footprint = r.need;
+        direct_running += 1;
+        stats.jobs_admitted += 1;
+        if (arena->used() > stats.peak_bytes) stats.peak_bytes = arena->used();
+      }
+    }
+    if (id) {
+      const dbscan_job j = records[id].job;
+      const uint64_t need = records[id].need;
+      lk.unlock();
+      dbscan_opts o = direct_opts(j, prune);
+      o.workspace = arena_base + off;  // arena offsets are multiples of 256
+      o.workspace_bytes = need;
+      int rc = dbscan_fit_ex(j.points, j.n, j.d, j.eps, j.minpts, j.labels, j.core, j.counts,
+                             (void *)ws, &o, nullptr);
+      // the call's device state opens its workspace: its status word says
+      // whether an input was not finite
+      unsigned status = 0;
+      if (rc == DBSCAN_OK) {
+        hipError_t e = hipMemcpyAsync(&status, o.workspace, sizeof(status),
+                                      hipMemcpyDeviceToHost, ws);
+        if (e == hipSuccess) e = hipStreamSynchronize(ws);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          rc = DBSCAN_E_DEVICE;
+        } else if (status & dbk::kStatusNonFinite) {
+          rc = DBSCAN_E_NONFINITE;
+        }
+      }
+      const int64_t t = now_ns();
+      lk.lock();
+      const bool done = rc == DBSCAN_OK || rc == DBSCAN_E_NONFINITE;  // labels -2 if non-finite
+      if (rc == DBSCAN_E_DEVICE) error = DBSCAN_E_DEVICE;
+      direct_running -= 1;
+      finish_locked(id, done ? DBSCAN_JOB_DONE : DBSCAN_JOB_FAILED, rc, t, 1);
+      cv.notify_all();
+      continue;
+    }
+    if (stopping && loop_done && direct_pending.empty()) break;
+    if (error != DBSCAN_OK) {
+      while (!direct_pending.empty()) {
+        finish_locked(direct_pending.front(), DBSCAN_JOB_FAILED, error, now_ns(), 1);
+        direct_pending.pop_front();
+      }
+      cv.notify_all();
+      if (stopping && loop_done) break;
+    }
+    cv.wait_for(lk, std::chrono::milliseconds(1));
   }
-  dbscan_stats st{};
-  const int rc = dbscan_fit_ex(j.points, j.n, j.d, j.eps, j.minpts, j.labels, j.core, j.counts,
-                               (void *)stream, nullptr, &st);
-  const int64_t t = now_ns();
-  std::lock_guard<std::mutex> lk(mu);
-  const bool done = rc == DBSCAN_OK || rc == DBSCAN_E_NONFINITE;  // labels -2 on non-finite input
-  finish_locked(id, done ? DBSCAN_JOB_DONE : DBSCAN_JOB_FAILED, rc, t, 1);
 }
 
 // Move queued jobs into free slots while their footprint fits (FIFO).
@@ -238,6 +349,7 @@ bool dbscan_server::admit_locked(std::vector<int> &fresh) {
     pending.pop_front();
     r.slot = slot;
     r.arena_off = off;
+    r.held = r.layout.total;
     slot_job[slot] = id;
     r.status.state = DBSCAN_JOB_RUNNING;
     r.status.t_admit_ns = now_ns();
@@ -251,15 +363,16 @@ bool dbscan_server::admit_locked(std::vector<int> &fresh) {
 
 void dbscan_server::loop() {
   if (hipSetDevice(device) != hipSuccess) {
+    std::lock_guard<std::mutex> g(mu);
     error = DBSCAN_E_DEVICE;
+    loop_done = true;
+    cv.notify_all();
     return;
   }
   std::vector<int> fresh;
-  std::vector<uint64_t> standalone;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     fresh.clear();
-    standalone.clear();
     admit_locked(fresh);
     bool active = false;
     for (int s = 0; s < nslots; ++s) active |= slot_job[s] != 0;
@@ -278,10 +391,6 @@ void dbscan_server::loop() {
     for (int s : fresh) {
       const uint64_t id = slot_job[s];
       Record &r = records[id];
-      if (!r.layout.persistent) {
-        standalone.push_back(id);
-        continue;
-      }
       const ServeLayout &L = r.layout;
       char *ws = arena_base + r.arena_off;
       dbk::JobDesc jd{};
@@ -352,11 +461,10 @@ void dbscan_server::loop() {
                            hipMemcpyHostToDevice, stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host staging buffers reused
-    for (uint64_t id : standalone) run_standalone(id);
     bool persistent_active = false;
     lk.lock();
     for (int s = 0; s < nslots; ++s)
-      if (slot_job[s] && records[slot_job[s]].layout.persistent) persistent_active = true;
+      if (slot_job[s]) persistent_active = true;
     lk.unlock();
     if (persistent_active && e == hipSuccess) {
       const int64_t t0 = now_ns();
@@ -383,31 +491,35 @@ void dbscan_server::loop() {
       break;
     }
     // harvest
-    std::vector<uint64_t> retry;
     for (int s = 0; s < nslots; ++s) {
       const uint64_t id = slot_job[s];
-      if (!id || !records[id].layout.persistent) continue;
+      if (!id) continue;
       const dbk::JobSched &js = h_sched[s];
       if (js.state == dbk::kJobDone) {
         const int err = (js.fail_status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
         finish_locked(id, DBSCAN_JOB_DONE, err, dev_to_host(js.t_done), 0);
       } else if (js.state == dbk::kJobFailed) {
-        // pair/band list overflow or inputs outside the FP16 range: redo it
-        // with the standalone path (same results)
+        // pair/band list overflow or inputs outside the FP16 range: the job
+        // moves to the front of the workers' queue (same results)
         Record &r = records[id];
         slot_job[s] = 0;
         r.slot = -1;
-        arena->release(r.arena_off, r.layout.total);
-        retry.push_back(id);
+        arena->release(r.arena_off, r.held);
+        r.held = 0;
+        r.direct = true;
+        int rc = DBSCAN_OK;
+        r.need = direct_bytes(r.job, prune, &rc);
+        if (rc != DBSCAN_OK || r.need > budget) {
+          finish_locked(id, DBSCAN_JOB_FAILED, rc != DBSCAN_OK ? rc : DBSCAN_E_NOMEM, now_ns(), 1);
+        } else {
+          r.status.state = DBSCAN_JOB_QUEUED;
+          direct_pending.push_front(id);
+        }
       }
-    }
-    if (!retry.empty()) {
-      lk.unlock();
-      for (uint64_t id : retry) run_standalone(id);
-      lk.lock();
     }
     cv.notify_all();
   }
+  loop_done = true;
   cv.notify_all();
 }
 
@@ -434,6 +546,23 @@ int dbscan_server_create(int device, uint64_t hbm_budget_bytes, int32_t max_slot
             hipMalloc((void **)&s->d_sched, sizeof(dbk::JobSched) * max_slots) == hipSuccess &&
             hipMalloc((void **)&s->d_clock, sizeof(long long)) == hipSuccess &&
             hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+  // tuning: DBSCAN_SERVE_WORKERS (1-8 worker streams), DBSCAN_SERVE_PRUNE=0
+  // (no tile pruning on the workers), DBSCAN_SERVE_LOOP_MAX_N (largest n the
+  // persistent loop takes)
+  if (const char *v = getenv("DBSCAN_SERVE_WORKERS")) {
+    const int w = atoi(v);
+    if (w >= 1 && w <= kMaxWorkers) s->nworkers = w;
+  }
+  if (const char *v = getenv("DBSCAN_SERVE_PRUNE")) s->prune = atoi(v) != 0;
+  if (const char *v = getenv("DBSCAN_SERVE_LOOP_MAX_N")) {
+    const long long m = atoll(v);
+    if (m >= 0) s->loop_max_n = m;
+  }
+  for (int w = 0; ok && w < s->nworkers; ++w) {
+    hipStream_t ws = nullptr;
+    ok = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) == hipSuccess;
+    if (ok) s->wstreams.push_back(ws);
+  }
   if (ok) {
     s->h_sched.assign(max_slots, dbk::JobSched{});
     s->slot_job.assign(max_slots, 0);
@@ -465,12 +594,14 @@ int dbscan_server_create(int device, uint64_t hbm_budget_bytes, int32_t max_slot
     if (s->d_sched) (void)hipFree(s->d_sched);
     if (s->d_clock) (void)hipFree(s->d_clock);
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    for (hipStream_t ws : s->wstreams) (void)hipStreamDestroy(ws);
     delete s;
     return DBSCAN_E_NOMEM;
   }
   s->arena = new Arena(s->budget);
   s->stats.budget_bytes = s->budget;
   s->worker = std::thread([s] { s->loop(); });
+  for (int w = 0; w < s->nworkers; ++w) s->workers.emplace_back([s, w] { s->work(w); });
   *out = s;
   return DBSCAN_OK;
 }
@@ -480,20 +611,29 @@ int dbscan_batch_submit(dbscan_server *s, const dbscan_job *job, uint64_t *job_i
   if (!job->points || !job->labels || !job->core || !job->counts) return DBSCAN_E_INVAL;
   if (job->n < 1 || job->n > DBSCAN_MAX_N || job->d < 1 || job->d > 1024) return DBSCAN_E_INVAL;
   if (!(job->eps >= 0.0) || !isfinite(job->eps) || job->minpts < 1) return DBSCAN_E_INVAL;
-  const ServeLayout L = serve_layout(*job);
-  if (L.total > s->budget) return DBSCAN_E_NOMEM;  // could never be admitted
+  if (job->precision < DBSCAN_PREC_AUTO || job->precision > DBSCAN_PREC_FP16) return DBSCAN_E_INVAL;
+  const ServeLayout L = serve_layout(*job, s->loop_max_n);
+  uint64_t need = L.total;
+  if (!L.persistent) {
+    int rc = DBSCAN_OK;
+    need = direct_bytes(*job, s->prune, &rc);
+    if (rc != DBSCAN_OK) return rc;  // e.g. a matrix-core precision for d > 76
+  }
+  if (need > s->budget) return DBSCAN_E_NOMEM;  // could never be admitted
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->error != DBSCAN_OK) return s->error;
-  if ((int)s->pending.size() >= kMaxQueue) return DBSCAN_E_AGAIN;
+  if ((int)(s->pending.size() + s->direct_pending.size()) >= kMaxQueue) return DBSCAN_E_AGAIN;
   const uint64_t id = s->next_id++;
   Record &r = s->records[id];
   r.job = *job;
   r.layout = L;
+  r.direct = !L.persistent;
+  r.need = need;
   r.status.state = DBSCAN_JOB_QUEUED;
   r.status.t_submit_ns = now_ns();
-  r.status.footprint = L.total;
+  r.status.footprint = need;
   r.status.tag = job->tag;
-  s->pending.push_back(id);
+  (r.direct ? s->direct_pending : s->pending).push_back(id);
   s->stats.jobs_submitted += 1;
   *job_id = id;
   s->cv.notify_all();
@@ -506,7 +646,10 @@ int dbscan_batch_poll(dbscan_server *s, uint64_t job_id, dbscan_job_status *st) 
   auto it = s->records.find(job_id);
   if (it == s->records.end()) return DBSCAN_E_INVAL;
   *st = it->second.status;
-  if (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) return DBSCAN_OK;
+  if (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) {
+    s->records.erase(it);  // a finished job's status is returned once
+    return DBSCAN_OK;
+  }
   return DBSCAN_PENDING;
 }
 
@@ -519,13 +662,19 @@ int dbscan_batch_wait(dbscan_server *s, uint64_t job_id, int64_t timeout_ns,
     auto it = s->records.find(job_id);
     if (it == s->records.end()) return DBSCAN_E_INVAL;
     *st = it->second.status;
-    if (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) return DBSCAN_OK;
+    if (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) {
+      s->records.erase(it);  // a finished job's status is returned once
+      return DBSCAN_OK;
+    }
     if (s->error != DBSCAN_OK) return s->error;
     if (s->cv.wait_until(lk, until) == std::cv_status::timeout) {
       it = s->records.find(job_id);
       *st = it->second.status;
-      return (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) ? DBSCAN_OK
-                                                                              : DBSCAN_PENDING;
+      if (st->state == DBSCAN_JOB_DONE || st->state == DBSCAN_JOB_FAILED) {
+        s->records.erase(it);
+        return DBSCAN_OK;
+      }
+      return DBSCAN_PENDING;
     }
   }
 }
@@ -534,8 +683,8 @@ int dbscan_server_get_stats(dbscan_server *s, dbscan_server_stats *out) {
   if (!s || !out) return DBSCAN_E_INVAL;
   std::lock_guard<std::mutex> lk(s->mu);
   *out = s->stats;
-  out->queued = (int64_t)s->pending.size();
-  int running = 0;
+  out->queued = (int64_t)(s->pending.size() + s->direct_pending.size());
+  int running = s->direct_running;
   for (int i = 0; i < s->nslots; ++i) running += s->slot_job[i] != 0;
   out->running = running;
   out->arena_used = s->arena->used();
@@ -550,9 +699,15 @@ int dbscan_server_destroy(dbscan_server *s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (auto &w : s->workers)
+    if (w.joinable()) w.join();
   const int err = s->error;
   (void)hipSetDevice(s->device);
   (void)hipStreamSynchronize(s->stream);
+  for (hipStream_t ws : s->wstreams) {
+    (void)hipStreamSynchronize(ws);
+    (void)hipStreamDestroy(ws);
+  }
   (void)hipFree(s->arena_base);
   (void)hipFree(s->d_jobs);
   (void)hipFree(s->d_sched);

@@ -118,11 +118,13 @@ def test_served_rejects_and_fallbacks():
 def test_served_jobs_arriving_while_others_run():
     """Submit a large job, then small ones while it runs: the small ones are
     admitted at epoch boundaries and finish before the large one."""
-    big = wl.blobs2d_200k(0, n=120_000)
-    big_eps, big_minpts = 0.1, 10  # sparse enough for the served pair list
+    # 200,000 points at d = 64 in float32 (no matrix cores, no pruning):
+    # tens of milliseconds on a worker
+    big = wl.mix64d_300k(0, n=200_000, eps_rule="q50")
+    big_eps, big_minpts = big.eps, big.minpts
     small = _mixed_jobs(6, seed=12, n_max=2000)
     with pkg.Server(max_slots=16) as srv:
-        jb = srv.submit(_gpu(big.points), big_eps, big_minpts)
+        jb = srv.submit(_gpu(big.points), big_eps, big_minpts, precision="fp32")
         ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in small]
         sts = [srv.wait(i, timeout=120) for i in ids]
         sb = srv.wait(jb, timeout=120)
@@ -130,11 +132,12 @@ def test_served_jobs_arriving_while_others_run():
         ob = _host(srv.outputs(jb))
     states = [(s["state"], s["error"]) for s in sts + [sb]]
     assert all(st == (pkg._lib.JOB_DONE, 0) for st in states), states
-    assert sb["fallback"] == 0
+    assert sb["fallback"] == 1  # a worker runs it, beside the loop
+    assert all(s["fallback"] == 0 for s in sts)
     assert max(s["t_done_ns"] for s in sts) < sb["t_done_ns"]
     for (pts, eps, mp), got in zip(small, outs):
         np.testing.assert_array_equal(got[0], orc.dbscan(pts, eps, mp)[0])
-    alone = _host(pkg.fit(_gpu(big.points), big_eps, big_minpts))
+    alone = _host(pkg.fit(_gpu(big.points), big_eps, big_minpts, precision="fp32"))
     for a, b in zip(ob, alone):
         np.testing.assert_array_equal(a, b)
 
@@ -144,7 +147,8 @@ def test_served_full_recipe_jobs():
     to 1.6e5) in one server: every output equals the oracle's element by
     element (digests written by the C oracle)."""
     from helpers import assert_golden, golden_job
-    loop = [1, 3, 9, 10, 18, 21, 23]  # jobs that must run inside the persistent loop
+    loop = [1, 10, 18, 21, 23]  # n <= 9,275, d = 2, 64, 3, 16, 64: the persistent loop
+    workers = [3, 9]            # n = 147,911 (d = 64), 158,412 (d = 3): a worker
     jobs = {j: wl.served_job(j) for j in range(32)}
     with pkg.Server(max_slots=32) as srv:
         ids = {j: srv.submit(_gpu(w.points), w.eps, w.minpts) for j, w in jobs.items()}
@@ -154,5 +158,73 @@ def test_served_full_recipe_jobs():
         assert st["state"] == pkg._lib.JOB_DONE and st["error"] == 0, (j, st)
     for j in loop:
         assert sts[j]["fallback"] == 0, j
+    for j in workers:
+        assert sts[j]["fallback"] == 1, j
     for j, w in jobs.items():
         assert_golden(golden_job(j), w.points, outs[j], f"served job {j}")
+
+
+@pytest.mark.parametrize("prec", ["auto", "fp32", "fp16", "bf16"])
+def test_served_precision(prec):
+    """dbscan_job.precision: every precision gives the oracle's outputs; the
+    loop runs float32 (d <= 4) and FP16 (16 <= d <= 76) jobs, the workers
+    the rest (BF16, float32 at d >= 16)."""
+    jobs = _mixed_jobs(12, seed=31, n_max=5000)
+    if prec in ("fp16", "bf16"):
+        jobs = [j for j in jobs if j[0].shape[1] >= 16]
+    with pkg.Server(max_slots=16) as srv:
+        ids = [srv.submit(_gpu(p), eps, mp, precision=prec) for p, eps, mp in jobs]
+        sts = [srv.wait(i, timeout=120) for i in ids]
+        outs = [_host(srv.outputs(i)) for i in ids]
+    for (pts, eps, mp), got, st in zip(jobs, outs, sts):
+        assert st["state"] == pkg._lib.JOB_DONE and st["error"] == 0
+        d = pts.shape[1]
+        in_loop = (d <= 4 and prec in ("auto", "fp32")) or (d >= 16 and prec in ("auto", "fp16"))
+        if not in_loop:
+            assert st["fallback"] == 1, (d, prec, st)
+        ref = orc.dbscan(pts, eps, mp)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, np.asarray(b).astype(a.dtype), err_msg=f"{prec} d={d}")
+
+
+def test_served_precision_rejected_for_wide_d():
+    with pkg.Server(max_slots=4) as srv:
+        with pytest.raises(pkg.DbscanError) as ei:
+            srv.submit(_gpu(np.zeros((100, 100), np.float32)), 1.0, 3, precision="fp16")
+        assert ei.value.code == pkg._lib.DBSCAN_E_UNSUPPORTED
+
+
+def test_served_small_jobs_do_not_wait_behind_large_ones():
+    """Large jobs run on the workers and a job whose lists overflow in the
+    loop moves to them too: small jobs submitted after them still finish
+    first, in the loop (the large job: 200,000 points at d = 64 in float32,
+    tens of milliseconds)."""
+    big = wl.mix64d_300k(0, n=200_000, eps_rule="q50")
+    rng = np.random.default_rng(4)
+    dense = rng.uniform(0, 1, size=(8000, 3)).astype(np.float32)  # eps 5: pair list overflows
+    small = _mixed_jobs(16, seed=41, n_max=3000)
+    with pkg.Server(max_slots=32) as srv:
+        jb = srv.submit(_gpu(big.points), big.eps, big.minpts, precision="fp32")
+        jd = srv.submit(_gpu(dense), 5.0, 3)
+        ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in small]
+        sts = [srv.wait(i, timeout=120) for i in ids]
+        sb, sd = srv.wait(jb, timeout=120), srv.wait(jd, timeout=120)
+        outs = [_host(srv.outputs(i)) for i in ids]
+        od = _host(srv.outputs(jd))
+    assert sb["fallback"] == 1 and sd["fallback"] == 1
+    assert all(s["fallback"] == 0 and s["state"] == pkg._lib.JOB_DONE for s in sts)
+    assert max(s["t_done_ns"] for s in sts) < sb["t_done_ns"]
+    for (pts, eps, mp), got in zip(small, outs):
+        np.testing.assert_array_equal(got[0], orc.dbscan(pts, eps, mp)[0])
+    assert (od[0] == 0).all() and (od[2] == 8000).all()
+
+
+def test_finished_status_is_returned_once():
+    pts = np.random.default_rng(1).uniform(0, 1, size=(500, 2)).astype(np.float32)
+    with pkg.Server(max_slots=4) as srv:
+        j = srv.submit(_gpu(pts), 0.05, 3)
+        st = srv.wait(j, timeout=60)
+        assert st["state"] == pkg._lib.JOB_DONE
+        with pytest.raises(pkg.DbscanError) as ei:
+            srv.poll(j)
+        assert ei.value.code == pkg._lib.DBSCAN_E_INVAL
