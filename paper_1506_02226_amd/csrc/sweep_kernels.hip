@@ -1,8 +1,9 @@
 // Row-uniform sweeps of the on-the-fly form (Section IV-B.1: the distance is
 // fused with the neighbourhood test and never stored).  One wave owns R rows
-// -- the "goal points" of Section IV-A.3, kept in scalar registers for
-// d <= 4 or in LDS otherwise -- and the 64 lanes hold 64 columns, so one
-// compare yields one 64-bit ballot word of the primitive cluster of a row.
+// -- the "goal points" of Section IV-A.3, kept in vector registers (the same
+// value in every lane) for d <= 4 or read from LDS as broadcasts otherwise --
+// and the 64 lanes hold 64 columns, so one compare yields one 64-bit ballot
+// word of the primitive cluster of a row.
 //
 //  * k_count_tri: step 1 + counts, each unordered pair tested once; also
 //    appends every neighbour pair (i, j), j < i, to a pair list (the input of
