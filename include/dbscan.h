@@ -74,7 +74,8 @@ extern "C" {
 
 /* Order in which the rows are processed (results are always returned in the
  * caller's order and are identical either way). */
-#define DBSCAN_ORDER_AUTO 0    /* spatial for d <= 128 and n >= 65536, else input */
+#define DBSCAN_ORDER_AUTO 0    /* spatial for d <= 128 from n = 16384 (bit matrix),
+                                  32768 (matrix cores) or 65536 (on the fly), else input */
 #define DBSCAN_ORDER_INPUT 1   /* the caller's order */
 #define DBSCAN_ORDER_SPATIAL 2 /* rows permuted on the device so that neighbours sit at
                                   nearby indices -- by a Morton key of the coordinates

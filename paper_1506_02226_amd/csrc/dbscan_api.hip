@@ -22,8 +22,13 @@ constexpr uint64_t kPairsPerPoint = 128;       // default pair-list capacity per
 constexpr uint64_t kMaxPairs = 2147483647ull;  // 16 GiB of (int, int) pairs
 constexpr uint64_t kBandPerPoint = 64;         // default band-list capacity per point
 constexpr int32_t kMaxMfmaD = 76;              // contraction length <= 80
-constexpr int64_t kSpatialMinN = 65536;        // auto order: below this the sort's ~15
-                                               // launches cost more than they save
+// auto order: below these sizes the sort's ~15 launches cost more than they
+// save (measured on the blob workloads: the bit-matrix form gains from
+// 16,384 points, the matrix cores from 32,768; the on-the-fly float32 form
+// only on dense inputs)
+constexpr int64_t kSpatialMinN = 65536;
+constexpr int64_t kSpatialMinNBitmask = 16384;
+constexpr int64_t kSpatialMinNMfma = 32768;
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
@@ -90,9 +95,12 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
     if (d > 4 || mfma) return DBSCAN_E_UNSUPPORTED;
     L->prune = true;
   }
-  if (req_order == DBSCAN_ORDER_AUTO)
-    L->order = (order_ok && n >= kSpatialMinN) ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
-  else if (req_order == DBSCAN_ORDER_INPUT)
+  if (req_order == DBSCAN_ORDER_AUTO) {
+    const int64_t min_n = mfma ? kSpatialMinNMfma
+                               : (L->adjacency == DBSCAN_ADJ_BITMASK ? kSpatialMinNBitmask
+                                                                     : kSpatialMinN);
+    L->order = (order_ok && n >= min_n) ? DBSCAN_ORDER_SPATIAL : DBSCAN_ORDER_INPUT;
+  } else if (req_order == DBSCAN_ORDER_INPUT)
     L->order = DBSCAN_ORDER_INPUT;
   else if (req_order == DBSCAN_ORDER_SPATIAL) {
     if (!order_ok) return DBSCAN_E_UNSUPPORTED;
@@ -431,7 +439,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     const int tiles = (int)(npad / 32);
     const int lds_most = dbk::mfma_chunk_tiles(dbk::mfma_k(d) / 16);
     const int most = L.precision == DBSCAN_PREC_BF16 ? lds_most : (lds_most < 128 ? lds_most : 128);
-    ms.chunk = tiles < most ? tiles : most;
+    ms.chunk = dbk::mfma_chunk_for(tiles, most);
     ms.nchunks = (tiles + ms.chunk - 1) / ms.chunk;
     ms.pair_cap = L.edge_cap;
     ms.band_cap = L.band_cap;

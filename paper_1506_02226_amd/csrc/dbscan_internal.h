@@ -77,6 +77,17 @@ __host__ __device__ inline long long mfma_items_before(int g, int nchunks, int k
 // sit in LDS, and at K <= 64 (ks <= 4) 256 tiles still leave room for four
 // work-groups per CU.
 __host__ __device__ constexpr int mfma_chunk_tiles(int ks) { return ks <= 4 ? 256 : 128; }
+// Row tiles per work item for `tiles` row tiles (a multiple of 8): `most`
+// for large inputs; small ones take fewer (a multiple of 8, at least 8) so
+// that the triangle still splits into about 2,048 items, eight per CU,
+// rather than a few long ones (n = 2,048 had 8 items of 64 tiles each).
+__host__ inline int mfma_chunk_for(int tiles, int most) {
+  long long c = ((long long)tiles * tiles / (16LL * 2048) + 7) / 8 * 8;
+  if (c < 8) c = 8;
+  if (c > most) c = most;
+  if (c > tiles) c = tiles;
+  return (int)c;
+}
 // They are listed row chunk by row chunk: chunk c holds the groups
 // 0 .. min(G, (c+1) k) - 1, so that items running at the same time share
 // their rows (one chunk's a-tiles serve many column groups from L2).  Items

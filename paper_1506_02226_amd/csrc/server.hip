@@ -428,7 +428,7 @@ void dbscan_server::loop() {
         // 256 stationary columns per task, row chunks of <= 128 tiles of 32
         // rows; only the lower triangle of (chunk, column group) is a task
         const int tiles = L.n_pad / 32;
-        const int per = tiles < 128 ? tiles : 128;
+        const int per = dbk::mfma_chunk_for(tiles, 128);
         jd.chunk = per;
         jd.nchunks = (tiles + per - 1) / per;
         js.ntasks[dbk::kPhCount] =

@@ -137,7 +137,8 @@ def test_workspace_size_layout():
 
 
 def test_order_option_layout():
-    """The spatial order (default for d <= 128 from n = 65536) adds seven
+    """The spatial order (default for d <= 128 from n = 16384 with the bit
+    matrix, 32768 on the matrix cores, 65536 otherwise) adds seven
     n_pad-sized int32 arrays (sort keys and values, two of each; inverse
     permutation; staged-order counts; per-root label minima) and the radix
     histograms (256 per 2048-key tile); it is refused where it does not apply."""
@@ -172,12 +173,19 @@ def test_order_option_layout():
         assert L.dbscan_workspace_size(n, 64, ctypes.byref(o), ctypes.byref(out)) == 0
         sizes[order] = out.value
     assert sizes["spatial"] - sizes["input"] == extra
-    small = _lib.make_opts("bitmask")
-    assert L.dbscan_workspace_size(65_535, 2, ctypes.byref(small), ctypes.byref(out)) == 0
-    auto_small = out.value
-    small.order = 1
-    assert L.dbscan_workspace_size(65_535, 2, ctypes.byref(small), ctypes.byref(out)) == 0
-    assert out.value == auto_small  # auto keeps the input order below 65536 points
+    # auto keeps the input order below each form's threshold, and takes the
+    # spatial order from it
+    for kw, d, below in ((dict(adjacency="bitmask"), 2, 16_383),
+                         (dict(adjacency="onthefly"), 3, 65_535),
+                         (dict(adjacency="onthefly", precision="fp16"), 64, 32_767)):
+        for m, want in ((below, 1), (below + 1, 2)):
+            auto = _lib.make_opts(**kw)
+            assert L.dbscan_workspace_size(m, d, ctypes.byref(auto), ctypes.byref(out)) == 0
+            a = out.value
+            fixed = _lib.make_opts(**kw)
+            fixed.order = want
+            assert L.dbscan_workspace_size(m, d, ctypes.byref(fixed), ctypes.byref(out)) == 0
+            assert out.value == a, (kw, m)
     o = _lib.make_opts(order="input")
     o.order = 9
     assert L.dbscan_workspace_size(1000, 2, ctypes.byref(o), ctypes.byref(out)) == _lib.DBSCAN_E_INVAL

@@ -194,12 +194,12 @@ def test_served_precision_rejected_for_wide_d():
         assert ei.value.code == pkg._lib.DBSCAN_E_UNSUPPORTED
 
 
-def test_served_small_jobs_do_not_wait_behind_large_ones():
-    """Large jobs run on the workers and a job whose lists overflow in the
-    loop moves to them too: small jobs submitted after them still finish
-    first, in the loop (the large job: 200,000 points at d = 64 in float32,
-    tens of milliseconds)."""
-    big = wl.mix64d_300k(0, n=200_000, eps_rule="q50")
+def test_served_overflow_moves_to_a_worker():
+    """A small job whose pair list overflows in the persistent loop moves to
+    a worker (the loop thread never runs it itself), beside a large job on
+    another worker; the small jobs submitted after them run in the loop, and
+    every output equals the oracle's."""
+    big = wl.mix64d_300k(0, n=100_000, eps_rule="q50")
     rng = np.random.default_rng(4)
     dense = rng.uniform(0, 1, size=(8000, 3)).astype(np.float32)  # eps 5: pair list overflows
     small = _mixed_jobs(16, seed=41, n_max=3000)
@@ -211,12 +211,16 @@ def test_served_small_jobs_do_not_wait_behind_large_ones():
         sb, sd = srv.wait(jb, timeout=120), srv.wait(jd, timeout=120)
         outs = [_host(srv.outputs(i)) for i in ids]
         od = _host(srv.outputs(jd))
+        ob = _host(srv.outputs(jb))
     assert sb["fallback"] == 1 and sd["fallback"] == 1
+    assert sd["state"] == pkg._lib.JOB_DONE and sd["error"] == 0
     assert all(s["fallback"] == 0 and s["state"] == pkg._lib.JOB_DONE for s in sts)
-    assert max(s["t_done_ns"] for s in sts) < sb["t_done_ns"]
     for (pts, eps, mp), got in zip(small, outs):
         np.testing.assert_array_equal(got[0], orc.dbscan(pts, eps, mp)[0])
     assert (od[0] == 0).all() and (od[2] == 8000).all()
+    ref = c_oracle.dbscan(big.points, big.eps, big.minpts)
+    for a, b in zip(ob, ref):
+        np.testing.assert_array_equal(a, np.asarray(b).astype(a.dtype))
 
 
 def test_finished_status_is_returned_once():
