@@ -213,9 +213,10 @@ int dbscan_fit_noalloc(const float *points, int64_t n, int32_t d, double eps, in
 
 /*
  * dbscan_workspace_size -- bytes of device scratch dbscan_fit_ex needs for
- * (n, d, opts); *bytes (HOST) receives the size.  The bitmask adjacency needs
- * n_pad * n_pad / 8 bytes plus a flag byte per 32 x 64 tile (n_pad^2 / 2048),
- * n_pad = ceil(n/256)*256; the on-the-fly form needs O(n*d).
+ * (n, d, opts); *bytes (HOST) receives the size.  The bitmask adjacency keeps
+ * one triangle of the relation, n_pad^2 / 16 + 4 n_pad bytes, plus a flag
+ * byte per 32 x 64 tile (n_pad^2 / 2048), n_pad = ceil(n/256)*256; the
+ * on-the-fly form needs O(n*d).
  */
 int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_t *bytes);
 

@@ -96,7 +96,7 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     uint32_t cnt2[R / 2];
 #pragma unroll
     for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
-    uint32_t *out = adj + (size_t)(row0 / R) * sc.n_pad;
+    uint32_t *out = adj + adj_block_base(row0 / R, sc.n_pad);  // indexed by column, from diag
     uint8_t *flag = tiles[(row0 - g0) / R];  // [column block - c0 / 64]
     float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
     if (PRUNE) {
@@ -322,7 +322,7 @@ __device__ __forceinline__ void for_flagged_words(const uint32_t *__restrict__ a
           qs[u] = qf + __builtin_ctzll(pend);
           pend &= pend - 1ull;
         }
-        wv[u] = (qs[u] < m.q1) ? adj[(size_t)qs[u] * n_pad + m.i] : 0u;
+        wv[u] = (qs[u] < m.q1) ? adj[adj_index(qs[u], m.i, n_pad)] : 0u;
       }
 #pragma unroll
       for (int u = 0; u < kMergeLoads; ++u) f(qs[u], lower_word(m, qs[u], wv[u]));

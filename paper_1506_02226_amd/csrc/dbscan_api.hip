@@ -52,7 +52,8 @@ struct Layout {
   int mfma_k = 0;        // contraction length of the matrix-core filter
 };
 
-uint64_t bitmask_bytes(int64_t n_pad) { return (uint64_t)n_pad / 32 * (uint64_t)n_pad * 4; }
+// the words of each 32-row block from its diagonal block on (dbk::adj_index)
+uint64_t bitmask_bytes(int64_t n_pad) { return dbk::adj_words((int)n_pad) * 4; }
 // one byte per 32 x 64 tile of the bitmask: non-empty or not
 uint64_t tile_flag_bytes(int64_t n_pad) { return (uint64_t)n_pad / 64 * (uint64_t)(n_pad / 32); }
 

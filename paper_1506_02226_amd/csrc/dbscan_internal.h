@@ -17,7 +17,7 @@ struct Buffers {
   int *parent;         // [n_pad] union-find forest
   int *jstar;          // [n_pad] lowest-index core neighbour of non-core points
   const int *list;     // [n_pad] compacted non-core rows
-  void *adjT;          // [n_pad/32][n_pad] uint32 bitmask adjacency (bitmask form only)
+  void *adjT;          // triangular uint32 bitmask adjacency (bitmask form only, adj_index)
   uint8_t *tflag;      // [n_pad/64][n_pad/32] non-empty flags of its 32 x 64 tiles
   int2 *pairs;         // [edge_cap] neighbour pairs (i, j), j < i (on-the-fly form)
   int2 *band;          // [band_cap] pairs the matrix-core filter leaves undecided
@@ -50,6 +50,24 @@ struct SweepScalars {
   float *box;          // tile pruning: boxes of the 64-point blocks, [2k][n_pad/64] lo / hi,
                        // then the same for row groups and for column chunks
 };
+
+// The bit matrix keeps, for each 32-row block q, the words of the columns j
+// from its 64-column diagonal block on (j >= 64 floor(q/2)): block q starts
+// after sum over q' < q of (n_pad - 64 floor(q'/2)) words, which is
+// q n_pad - 64 S(q) with S(2m) = m (m - 1) and S(2m + 1) = m^2.  About half
+// of the n_pad^2 / 32 words of the full square.
+__host__ __device__ inline long long adj_block_base(int q, int n_pad) {
+  const long long m = q >> 1;
+  const long long S = (q & 1) ? m * m : m * (m - 1);
+  return (long long)q * n_pad - 64 * S - 64 * m;  // word index of column 0 of block q
+}
+__host__ __device__ inline size_t adj_index(int q, int j, int n_pad) {
+  return (size_t)(adj_block_base(q, n_pad) + j);
+}
+__host__ inline unsigned long long adj_words(int n_pad) {
+  const long long nq = n_pad / 32, m = nq / 2;  // nq is even
+  return (unsigned long long)(nq * (long long)n_pad - 64 * m * (m - 1));
+}
 
 // Tile pruning: launch helpers of the persistent sweeps.
 hipError_t run_coarse_boxes(const SweepScalars &sc, hipStream_t s);

@@ -107,7 +107,11 @@ def test_workspace_size_layout():
     bm = _lib.make_opts("bitmask")
     assert L.dbscan_workspace_size(200_000, 2, ctypes.byref(bm), ctypes.byref(out)) == 0
     n_pad = 200_192
-    assert out.value >= n_pad * n_pad // 8
+    # the bit matrix keeps each 32-row block's words from its 64-column
+    # diagonal block on: n_pad^2 / 64 + n_pad words, plus a flag byte per
+    # 32 x 64 tile, plus O(n) sections
+    tri = 4 * (n_pad * n_pad // 64 + n_pad) + n_pad * n_pad // 2048
+    assert tri <= out.value < tri + 64 * n_pad
     # on the fly: O(n d) plus the pair list (8 bytes per pair, 128 pairs per point by default)
     fly = _lib.make_opts("onthefly")
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(fly), ctypes.byref(out)) == 0
