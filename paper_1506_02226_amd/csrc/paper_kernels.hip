@@ -317,11 +317,16 @@ __global__ __launch_bounds__(256) void k_merge_target(uint8_t *__restrict__ clus
   if (c == t || !alive[c]) return;
   const uint8_t *rc = cluster + (size_t)c * n;
   uint8_t *rt = cluster + (size_t)t * n;
+  // row t is read and set here by several blocks at once: relaxed byte
+  // atomics (plain byte loads and stores on the device) make that defined
   bool hit = false;
-  for (int k = threadIdx.x; k < n; k += 256) hit |= (rc[k] & rt[k] & core[k]) != 0;
+  for (int k = threadIdx.x; k < n; k += 256) {
+    const uint8_t v = __hip_atomic_load(rt + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hit |= (rc[k] & core[k] & v) != 0;
+  }
   if (!__syncthreads_or(hit)) return;
   for (int k = threadIdx.x; k < n; k += 256)
-    if (rc[k]) rt[k] = 1;
+    if (rc[k]) __hip_atomic_store(rt + k, (uint8_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (threadIdx.x == 0) {
     alive[c] = 0;
     *changed = 1;

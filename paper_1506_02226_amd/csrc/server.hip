@@ -267,9 +267,14 @@ void dbscan_server::finish_locked(uint64_t id, int32_t state, int32_t err, int64
 // stream (the call waits for that stream, so the device time of one job
 // overlaps with the other workers' jobs and with the loop's epochs).
 void dbscan_server::work(int w) {
-  if (hipSetDevice(device) != hipSuccess) return;
-  const hipStream_t ws = wstreams[w];
   std::unique_lock<std::mutex> lk(mu);
+  if (hipSetDevice(device) != hipSuccess) {
+    (void)hipGetLastError();
+    error = DBSCAN_E_DEVICE;  // the other threads fail the queued jobs
+    cv.notify_all();
+    return;
+  }
+  const hipStream_t ws = wstreams[w];
   for (;;) {
     uint64_t id = 0, off = 0;
     if (!direct_pending.empty() && error == DBSCAN_OK) {
@@ -310,6 +315,9 @@ void dbscan_server::work(int w) {
           rc = DBSCAN_E_NONFINITE;
         }
       }
+      // a failed call may have left work queued: the arena slice is released
+      // only once the stream holds nothing that uses it
+      if (rc != DBSCAN_OK && rc != DBSCAN_E_NONFINITE) (void)hipStreamSynchronize(ws);
       const int64_t t = now_ns();
       lk.lock();
       const bool done = rc == DBSCAN_OK || rc == DBSCAN_E_NONFINITE;  // labels -2 if non-finite
@@ -365,6 +373,10 @@ void dbscan_server::loop() {
   if (hipSetDevice(device) != hipSuccess) {
     std::lock_guard<std::mutex> g(mu);
     error = DBSCAN_E_DEVICE;
+    while (!pending.empty()) {
+      finish_locked(pending.front(), DBSCAN_JOB_FAILED, DBSCAN_E_DEVICE, now_ns(), 0);
+      pending.pop_front();
+    }
     loop_done = true;
     cv.notify_all();
     return;
