@@ -235,10 +235,15 @@ Tri tri_split(int64_t n_pad, int max_chunk) {
 }
 
 // Tiles of the step-1 sweep: triangular for d <= 4, column chunks otherwise.
+// For d <= 4 a block's column chunk is at most 2,048 points: every wave
+// re-reads the chunk for each 16 rows it holds, and 2,048-point chunks of
+// the blocks an XCD runs at once stay in its L2 (measured on the 2M-point
+// 3-D workload: 53 GB fetched past the L2 per launch instead of 315 GB,
+// same sweep time; 1,024-point chunks were 4% slower).
 dbk::SweepScalars sweep_tiles(const dbk::SweepScalars &sc, int64_t n, int64_t npad, int d,
                               int d_pad) {
   dbk::SweepScalars t = sc;
-  const Tri tr = tri_split(npad, 4096);
+  const Tri tr = tri_split(npad, d <= 4 ? 2048 : 4096);
   t.nchunks = tr.nchunks;
   t.chunk = tr.chunk;
   t.rgroup = tr.rgroup;
