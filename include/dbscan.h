@@ -160,6 +160,10 @@ typedef struct dbscan_stats {
                              the device) */
   int32_t order_used;     /* DBSCAN_ORDER_INPUT or DBSCAN_ORDER_SPATIAL */
   int32_t pruned;         /* 1 if tile pruning was on (dbscan_opts.prune) */
+  int32_t hoisted;        /* 1 if the float32 sweep tested the hoisted form
+                             (on the fly, d <= 4; dbscan_hoist_band), 0 for
+                             the direct form */
+  int32_t reserved0;
 } dbscan_stats;
 
 /*
@@ -201,7 +205,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
  * process ends.  The default plan is used when its workspace fits; otherwise
  * the on-the-fly form runs with pair and band lists sized to the array (a
  * full pair list makes step 3 repeat the epsilon tests; results are the
- * same).  DBSCAN_E_NOMEM when even that does not fit: n above 1,274,880 at
+ * same).  DBSCAN_E_NOMEM when even that does not fit: n above 890,112 at
  * d = 3, 388,608 at d = 16, 120,320 at d = 64.  Every call on a GPU uses that
  * GPU's one array: calls that overlap on one GPU (different streams, or
  * different host threads without ordering) race and must be serialized by
@@ -230,6 +234,21 @@ int dbscan_workspace_size(int64_t n, int32_t d, const dbscan_opts *opts, uint64_
  * IV-B.2 writes the squared distance as that sum).  lo, hi: HOST float*.
  */
 int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi);
+
+/*
+ * dbscan_hoist_band -- the float32 thresholds of one row of the hoisted test
+ * that the on-the-fly float32 sweep (d <= 4) makes: Section IV-B.2's
+ * T + P[n] - 2 t.p, taken about a local origin c (the centre of the box of
+ * the row's block of 16 staged rows).  For the row x, a = fl(x - c) with
+ * sq_norm = |a|^2 (float64), and for a column y, b = fl(y - c): the float32
+ * value q of |b|^2 - 2 a.b (2d roundings, any order, fused or not) with
+ * q <= *lo makes the pair a neighbour under the float64 definition, q > *hi
+ * makes it not one, and pairs in between are re-evaluated in float64.
+ * *lo is -inf when eps is too small beside |x - c| for a sure "in".
+ * Valid while every coordinate is at most 2^60 in magnitude (the sweep takes
+ * the direct form otherwise).  d in 1..4; lo, hi: HOST float*.
+ */
+int dbscan_hoist_band(double sq_norm, int32_t d, double eps2, float *lo, float *hi);
 
 /* ------------------------------------------------------------------ serving
  * A server runs the jobs of many callers on one GPU.  Small jobs (n up to

@@ -37,6 +37,7 @@ EXPORTS = (
     "dbscan_strerror",
     "dbscan_version",
     "dbscan_fp32_band",
+    "dbscan_hoist_band",
     "dbscan_server_create",
     "dbscan_batch_submit",
     "dbscan_batch_poll",
@@ -89,6 +90,8 @@ class Stats(ctypes.Structure):
         ("sweep1_tests", ctypes.c_int64),
         ("order_used", ctypes.c_int32),
         ("pruned", ctypes.c_int32),
+        ("hoisted", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -191,6 +194,9 @@ def load(path: str | None = None):
     L.dbscan_fp32_band.argtypes = [dbl, i32, ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float)]
     L.dbscan_fp32_band.restype = ctypes.c_int
+    L.dbscan_hoist_band.argtypes = [dbl, i32, dbl, ctypes.POINTER(ctypes.c_float),
+                                    ctypes.POINTER(ctypes.c_float)]
+    L.dbscan_hoist_band.restype = ctypes.c_int
     sp = ctypes.c_void_p
     L.dbscan_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, i32, ctypes.POINTER(sp)]
     L.dbscan_server_create.restype = ctypes.c_int

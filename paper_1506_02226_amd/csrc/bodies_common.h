@@ -5,6 +5,7 @@
 #pragma once
 
 #include "dbscan_device.h"
+#include "dbscan_internal.h"
 
 namespace dbk {
 
@@ -31,6 +32,48 @@ __device__ __forceinline__ void stage_soa_body(const float *__restrict__ pts, in
     soa[(size_t)k * n_pad + i] = v;
   }
   if (__ballot(bad) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNonFinite);
+}
+
+// Rows of the hoisted test (HoistView) for the staged coordinates: thread i
+// of the grid (n_pad threads) takes row i.  The 16 rows of a block are 16
+// lanes of one wave, so their box comes from lane shuffles (NaN padding
+// skipped).  A coordinate beyond 2^60 in magnitude (where |b|^2 and the
+// products could overflow) sets kStatusNoHoist: the sweep then takes the
+// direct form.
+__device__ __forceinline__ void hoist_prep_body(const float *__restrict__ soa, int n, int d,
+                                                int n_pad, double eps2, float *__restrict__ hoist,
+                                                DevState *st, int bid) {
+  const int i = bid * 256 + (int)threadIdx.x;  // every lane of the wave is a row
+  const HoistView<float> v = hoist_view(hoist, n_pad, d);
+  const int blk = i >> 4;
+  bool far = false;
+  double T = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const float x = soa[(size_t)k * n_pad + i];
+    far |= i < n && !(__builtin_fabsf(x) <= 0x1p60f);
+    float lo = x, hi = x;
+    for (int off = 1; off < 16; off <<= 1) {
+      lo = __builtin_fminf(lo, __shfl_xor(lo, off));
+      hi = __builtin_fmaxf(hi, __shfl_xor(hi, off));
+    }
+    const float c = 0.5f * lo + 0.5f * hi;
+    if ((i & 15) == 0) {
+      v.box[(size_t)(2 * k) * (n_pad / 16) + blk] = lo;
+      v.box[(size_t)(2 * k + 1) * (n_pad / 16) + blk] = hi;
+      v.cen[(size_t)k * (n_pad / 16) + blk] = c;
+    }
+    const float a = x - c;
+    v.a[(size_t)k * n_pad + i] = -2.0f * a;
+    T += (double)a * (double)a;
+  }
+  float lo, hi;
+  hoist_band(T, d, eps2, &lo, &hi);
+  v.lo[i] = lo;
+  v.hi[i] = hi;
+  float h = hi;
+  for (int off = 1; off < 8; off <<= 1) h = __builtin_fmaxf(h, __shfl_xor(h, off));
+  if ((i & 7) == 0) v.hg[i >> 3] = h;
+  if (__ballot(far) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNoHoist);
 }
 
 // Clears counts, parent = identity, jstar = none; with `soa`, also stages the

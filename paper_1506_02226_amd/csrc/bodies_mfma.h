@@ -119,13 +119,6 @@ __device__ __forceinline__ void mfma_prep_body(const float *__restrict__ pts, in
 }
 
 // ------------------------------------------------------------- thresholds
-// Neighbouring float32 values (finite x).
-__device__ __forceinline__ float next_down(float x) {
-  if (x == 0.0f) return -__uint_as_float(1u);
-  const unsigned b = __float_as_uint(x);
-  return __uint_as_float(x > 0.0f ? b - 1u : b + 1u);
-}
-__device__ __forceinline__ float next_up(float x) { return -next_down(-x); }
 
 // Bounds (all in float64, then rounded outward to float32):
 //   |x - x~| <= u |x| + sqrt(d) tiny per point, so |D - D~| <= Delta with

@@ -79,7 +79,15 @@ __device__ __forceinline__ void for_near_blocks(const SweepScalars &sc, int rows
 // rows' box (all 64 blocks of the chunk tested at once, one per lane).
 // Skipped pairs are provably not neighbours; the tests actually made go to
 // st->tests.
-template <int D, int R, bool EMIT, bool PRUNE = false, int QN = kListQueue>
+//
+// HOIST (sc.hoist, rows prepared by hoist_prep_body): the hoisted form of
+// Section IV-B.2 about the origin c of the wave's 16 rows.  Per 64-column
+// tile the wave forms b = fl(y - c) and P = |b|^2 once; per pair it adds
+// the row's -2a.b to P (d fused multiply-adds) and compares the result q
+// with the row's thresholds: q <= lo in, q > hi out, else float64 -- the
+// same decisions as the direct form at about half its instructions.  An
+// 8-row group is skipped when its smallest q exceeds the group's largest hi.
+template <int D, int R, bool EMIT, bool PRUNE = false, int QN = kListQueue, bool HOIST = false>
 __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
                                                int *__restrict__ counts,
                                                int2 *__restrict__ pairs,
@@ -107,24 +115,46 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     wave_box<D>(lbl, lbh, clo, chi);
     if (box_gap2<D>(rlo, rhi, clo, chi) > sc.hi) return;
   }
+  static_assert(!HOIST || R == 16, "the hoisted rows come in blocks of 16");
+  HoistView<const float> hv{};
+  if (HOIST) hv = hoist_view(sc.hoist, sc.n_pad, D);
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
   __syncthreads();
   WaveQueue qu{qbuf[w], 0, QN - 64};  // appended once QN - 64 pairs are queued
   unsigned long long tested = 0;  // PRUNE: pair tests made by this wave
+  constexpr int GR = R > 8 ? 8 : R;  // rows per group of the minimum test
   for (int row0 = g0 + w * R; row0 < g1; row0 += 4 * R) {
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
     if (cs >= c1) continue;  // wave-uniform
+    // the rows: coordinates (direct form) or -2 fl(x - c) (HOIST)
     float xr[R][D];
+    const float *rows = HOIST ? hv.a : soa;
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(soa[(size_t)k * sc.n_pad + row0 + r]);
+      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(rows[(size_t)k * sc.n_pad + row0 + r]);
+    float cen[D];         // HOIST: the rows' origin
+    float gate[R / GR];   // largest "out" threshold of each group
+#pragma unroll
+    for (int g = 0; g < R / GR; ++g) gate[g] = sc.hi;
+    if (HOIST) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) cen[k] = to_vgpr(hv.cen[(size_t)k * (sc.n_pad / 16) + row0 / 16]);
+#pragma unroll
+      for (int g = 0; g < R / GR; ++g) gate[g] = to_vgpr(hv.hg[row0 / GR + g]);
+    }
     int cnt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) cnt[r] = 0;
     float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
-    if (PRUNE) {
+    if (PRUNE && HOIST) {
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        rlo[k] = hv.box[(size_t)(2 * k) * (sc.n_pad / 16) + row0 / 16];
+        rhi[k] = hv.box[(size_t)(2 * k + 1) * (sc.n_pad / 16) + row0 / 16];
+      }
+    } else if (PRUNE) {
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         rlo[k] = xr[0][k];
@@ -140,21 +170,40 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     auto tile = [&](int cb, const float (&xc)[D]) {
       const bool off = cb != diag;
       uint32_t tally = 0;
+      // HOIST: the column about the rows' origin, and its squared norm
+      float bq[D], pn = 0.0f;
+      if (HOIST) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) bq[k] = xc[k] - cen[k];
+        pn = bq[0] * bq[0];
+#pragma unroll
+        for (int k = 1; k < D; ++k) pn = __builtin_fmaf(bq[k], bq[k], pn);
+      }
       // rows in groups of GR: one compare of their minimum and one branch
       // per group in the common case; the rows' own ballots only in the rare
-      constexpr int GR = R > 8 ? 8 : R;
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) {
         float sg[GR];
 #pragma unroll
-        for (int k = 0; k < GR; ++k) sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
-        if (__ballot(min_of<GR>(sg) <= sc.hi) == 0ull) continue;
+        for (int k = 0; k < GR; ++k) {
+          if (HOIST) {
+            float q = pn;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[g * GR + k][kk], bq[kk], q);
+            sg[k] = q;
+          } else {
+            sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
+          }
+        }
+        if (__ballot(min_of<GR>(sg) <= gate[g]) == 0ull) continue;
 #pragma unroll
         for (int k = 0; k < GR; ++k) {
           const int r = g * GR + k;
-          const uint64_t m = __ballot(sg[k] <= sc.hi);
+          const float hi_r = HOIST ? hv.hi[row0 + r] : sc.hi;
+          const float lo_r = HOIST ? hv.lo[row0 + r] : sc.lo;
+          const uint64_t m = __ballot(sg[k] <= hi_r);
           if (m == 0ull) continue;
-          const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
+          const uint64_t lo_m = __ballot(sg[k] <= lo_r);
           uint64_t in = m;
           if (lo_m != m)
             in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,

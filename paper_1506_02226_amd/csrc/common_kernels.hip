@@ -34,9 +34,11 @@ __global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, 
                         float *__restrict__ soa, int *__restrict__ counts,
                         int *__restrict__ parent, int *__restrict__ jstar, DevState *st,
                         const int *__restrict__ perm, int *__restrict__ inv,
-                        int *__restrict__ rootmin) {
+                        int *__restrict__ rootmin, float *__restrict__ hoist, double eps2) {
   stage_body(pts, n, d, n_pad, d_pad, soa, counts, parent, jstar, st, blockIdx.x, perm, inv,
              rootmin);
+  // each thread reads back only the coordinates it wrote itself
+  if (hoist) hoist_prep_body(soa, n, d, n_pad, eps2, hoist, st, blockIdx.x);
 }
 
 // ------------------------------------------------------------- core flags
@@ -163,9 +165,11 @@ hipError_t run_reset(DevState *st, long long pair_cap, hipStream_t s) {
 }
 
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
-                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s) {
+                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s,
+                     float *hoist, double eps2) {
+  if (hoist && (!soa || d > 4 || n_pad % 256 != 0)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_stage, dim3((n_pad + 255) / 256), dim3(256), 0, s, pts, n, d, n_pad, d_pad,
-                     soa, counts, parent, jstar, st, ord.perm, ord.inv, ord.rootmin);
+                     soa, counts, parent, jstar, st, ord.perm, ord.inv, ord.rootmin, hoist, eps2);
   return hipGetLastError();
 }
 

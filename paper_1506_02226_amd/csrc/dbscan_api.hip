@@ -47,6 +47,7 @@ struct Layout {
   uint64_t off_keys[2] = {0, 0}, off_vals[2] = {0, 0}, off_hist = 0, off_inv = 0,
            off_counts = 0, off_rootmin = 0;
   uint64_t off_box = 0;  // tile pruning: per-64-point-block boxes
+  uint64_t off_hoist = 0;  // rows of the hoisted float32 test (0: none)
   int64_t edge_cap = 0;  // pair-list entries (on-the-fly form, d <= 4 or matrix cores)
   int64_t band_cap = 0;  // band-list entries (matrix cores)
   int mfma_k = 0;        // contraction length of the matrix-core filter
@@ -147,6 +148,9 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   }
   // boxes of the 64-point blocks, then of the row groups and of the chunks
   if (L->prune) L->off_box = take((uint64_t)3 * 2 * d * (L->n_pad / 64) * 4);
+  // the on-the-fly float32 sweep for d <= 4 tests the hoisted form
+  if (!mfma && L->adjacency == DBSCAN_ADJ_ONTHEFLY && d <= 4)
+    L->off_hoist = take(dbk::hoist_floats((int)L->n_pad, d) * 4);
   L->total = off;
   return DBSCAN_OK;
 }
@@ -289,6 +293,12 @@ int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi) {
   return DBSCAN_OK;
 }
 
+int dbscan_hoist_band(double sq_norm, int32_t d, double eps2, float *lo, float *hi) {
+  if (!lo || !hi || d < 1 || d > 4 || !(eps2 >= 0.0) || !(sq_norm >= 0.0)) return DBSCAN_E_INVAL;
+  dbk::hoist_band(sq_norm, d, eps2, lo, hi);
+  return DBSCAN_OK;
+}
+
 const char *dbscan_strerror(int code) {
   switch (code) {
     case DBSCAN_OK: return "ok";
@@ -392,8 +402,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     counts_k = (int *)(ws + L.off_counts);
   }
   // the matrix-core path stages the float32 coordinates only if it falls back
+  float *hoist = L.off_hoist ? (float *)(ws + L.off_hoist) : nullptr;
   step(dbk::run_stage(points, ni, d, npad, L.d_pad, mfma ? nullptr : soa, counts_k, parent, jstar,
-                      st, ord, s));
+                      st, ord, s, hoist, eps * eps));
   const double band_rel = (opts && opts->band_rel > 0.0) ? opts->band_rel : kDefaultBandRel;
   if (mfma) {
     step(dbk::run_mfma_prep(points, ord.perm, ni, d, npad, L.precision, a_aug, b_aug, st, s));
@@ -425,6 +436,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   sc.edge_cap = L.edge_cap;
   sc.flags = 0;
   sc.box = nullptr;
+  sc.hoist = nullptr;
   if (L.prune) {
     float *box = (float *)(ws + L.off_box);
     step(dbk::run_block_boxes(soa, npad, d, box, s));
@@ -468,7 +480,8 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     step(dbk::run_bitmask(bufs, b1, s));
     mark(5);
   } else {
-    const dbk::SweepScalars c1 = sweep_tiles(sc, n, npad, d, L.d_pad);
+    dbk::SweepScalars c1 = sweep_tiles(sc, n, npad, d, L.d_pad);
+    c1.hoist = hoist;
     mark(4);
     step(dbk::run_count(bufs, c1, use_pairs, s));
     mark(5);
@@ -560,6 +573,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
                                  : sweep_tests(n, L.n_pad, d, L.adjacency == DBSCAN_ADJ_BITMASK,
                                                mfma);
   stats->pruned = L.prune ? 1 : 0;
+  stats->hoisted = (L.off_hoist && !(hst.status & dbk::kStatusNoHoist)) ? 1 : 0;
   stats->status = (hst.status & dbk::kStatusNonFinite) ? DBSCAN_E_NONFINITE : DBSCAN_OK;
   return stats->status;
 }

@@ -21,6 +21,7 @@ constexpr unsigned kStatusNonFinite = 1u;      // an input coordinate is NaN or 
 constexpr unsigned kStatusEdgeOverflow = 2u;   // the neighbour-pair list ran out of room
 constexpr unsigned kStatusBandOverflow = 4u;   // the matrix-core band list ran out of room
 constexpr unsigned kStatusRange = 8u;          // inputs outside the low-precision range
+constexpr unsigned kStatusNoHoist = 16u;       // a coordinate beyond the hoisted form's range
 
 constexpr int kPrecBf16 = 2;  // values of dbscan_opts.precision
 constexpr int kPrecFp16 = 3;
@@ -54,6 +55,14 @@ constexpr int kNoNeighbour = 0x7fffffff;
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Neighbouring float32 values (finite x).
+__device__ __forceinline__ float next_down(float x) {
+  if (x == 0.0f) return -__uint_as_float(1u);
+  const unsigned b = __float_as_uint(x);
+  return __uint_as_float(x > 0.0f ? b - 1u : b + 1u);
+}
+__device__ __forceinline__ float next_up(float x) { return -next_down(-x); }
 
 // Number of set bits of m below this lane.
 __device__ __forceinline__ int lanes_below(uint64_t m) {

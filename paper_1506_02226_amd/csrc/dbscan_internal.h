@@ -49,7 +49,92 @@ struct SweepScalars {
   int rgroup;          // rows per block of the triangular sweeps (multiple of 64)
   float *box;          // tile pruning: boxes of the 64-point blocks, [2k][n_pad/64] lo / hi,
                        // then the same for row groups and for column chunks
+  const float *hoist;  // rows of the hoisted test (hoist_view), or null: direct form
 };
+
+// Rows of the hoisted float32 test of the d <= 4 on-the-fly sweep (Section
+// IV-B.2's T + P[n] - 2 t.p, taken about a local origin): each 16-row block
+// of the staged order has an origin c (the centre of its box), and row i
+// keeps a = -2 fl(x_i - c) and its float32 thresholds (hoist_prep_body).
+// Layout (floats): a [k][n_pad], lo [n_pad], hi [n_pad], the blocks' boxes
+// [2k][n_pad/16] (lo, hi), their origins [k][n_pad/16], and per 8-row group
+// the largest hi [n_pad/8].
+// The float32 value next to finite x, upwards (dir = 1) or downwards (-1).
+__host__ __device__ inline float f32_step(float x, int dir) {
+  if (x == 0.0f) return dir > 0 ? 1.40129846e-45f : -1.40129846e-45f;
+  const unsigned b = __builtin_bit_cast(unsigned, x);
+  return __builtin_bit_cast(float, ((x > 0.0f) == (dir > 0)) ? b + 1u : b - 1u);
+}
+
+// Float32 thresholds of the hoisted test for one row.  With c the origin of
+// the row's block, a = fl(x - c) the row (T = |a|^2), b = fl(y - c) a
+// column and q the float32 value of |b|^2 - 2 a.b (2d roundings, any order,
+// fused or not), let t = |x - y| (exact) and r >= |x - c|.  Rounding the
+// shifted points moves |a - b| from t by at most u (2r + t), and
+// |q + T - |a - b|^2| <= g (r + t)(3r + t) + e, with g = gamma_2d (1 + u)^2
+// and e = 4d 2^-149 for gradual underflow.  Hence q <= G(t) and q >= F(t):
+//   G(t) = ((1 + u) t + 2ur)^2 + g (r + t)(3r + t) + e - T,
+//   F(t) = ((1 - u) t - 2ur)^2 - g (r + t)(3r + t) - e - T  ((1 - u) t >= 2ur).
+// G grows with t, and F from its vertex t_v on.  t_in and t_out bound the
+// exact distances at which the float64 value of the definition is surely
+// <= eps2 or surely > eps2 (the factors of band_fp32), so hi >= G(t_out)
+// makes q > hi "out" and lo <= F(t_in) makes q <= lo "in" (lo = -inf when
+// t_in is below t_v or 2ur / (1 - u)).  The double arithmetic is widened by
+// 2^-48 of the magnitudes and the results rounded outward.
+__host__ __device__ inline void hoist_band(double T, int d, double eps2, float *lo, float *hi) {
+  if (__builtin_isinf(eps2)) {
+    *lo = __builtin_inff();
+    *hi = __builtin_inff();
+    return;
+  }
+  const double u = 0x1p-24, u64 = 0x1p-53;
+  const double g = (2.0 * d * u / (1.0 - 2.0 * d * u)) * (1.0 + u) * (1.0 + u) * (1.0 + 0x1p-40);
+  const double e = 4.0 * d * 0x1p-149;
+  const double g64 = (d + 2) * u64 / (1.0 - (d + 2) * u64);
+  const double t_in = __builtin_sqrt(eps2 * (1.0 - 4 * u64) / (1.0 + g64)) * (1.0 - 0x1p-50);
+  const double t_out = __builtin_sqrt(eps2 * (1.0 + 4 * u64) / (1.0 - g64)) * (1.0 + 0x1p-50);
+  const double T_lo = T * (1.0 - 0x1p-50), T_hi = T * (1.0 + 0x1p-50);
+  const double r = __builtin_sqrt(T_hi) * (1.0 + 0x1p-50) / (1.0 - u);
+  const double wo = (1.0 + u) * t_out + 2.0 * u * r;
+  const double eo = g * (r + t_out) * (3.0 * r + t_out) + e;
+  double h = wo * wo + eo - T_lo;
+  h += 0x1p-48 * (wo * wo + eo + T_lo);
+  float hf = (float)h;
+  if ((double)hf < h) hf = __builtin_isinf(hf) ? -3.40282347e38f : f32_step(hf, 1);
+  *hi = hf;
+  const double A = (1.0 - u) * (1.0 - u) - g;
+  const double tv = (4.0 * u * (1.0 - u) * r + 4.0 * g * r) / (2.0 * A) * (1.0 + 0x1p-40);
+  const double wi = (1.0 - u) * t_in - 2.0 * u * r;
+  if (!(wi >= 0.0 && t_in >= tv)) {  // also for a NaN row (padding)
+    *lo = -__builtin_inff();
+    return;
+  }
+  const double ei = g * (r + t_in) * (3.0 * r + t_in) + e;
+  double l = wi * wi - ei - T_hi;
+  l -= 0x1p-48 * (wi * wi + ei + T_hi);
+  float lf = (float)l;
+  if ((double)lf > l) lf = __builtin_isinf(lf) ? 3.40282347e38f : f32_step(lf, -1);
+  *lo = lf;
+}
+
+template <typename F>
+struct HoistView {
+  F *a, *lo, *hi, *box, *cen, *hg;
+};
+__host__ __device__ inline unsigned long long hoist_floats(int n_pad, int d) {
+  return (unsigned long long)(d + 2) * n_pad + 3ull * d * (n_pad / 16) + n_pad / 8;
+}
+template <typename F>
+__host__ __device__ inline HoistView<F> hoist_view(F *base, int n_pad, int d) {
+  HoistView<F> v;
+  v.a = base;
+  v.lo = v.a + (size_t)d * n_pad;
+  v.hi = v.lo + n_pad;
+  v.box = v.hi + n_pad;
+  v.cen = v.box + (size_t)2 * d * (n_pad / 16);
+  v.hg = v.cen + (size_t)d * (n_pad / 16);
+  return v;
+}
 
 // The bit matrix keeps, for each 32-row block q, the words of the columns j
 // from its 64-column diagonal block on (j >= 64 floor(q/2)): block q starts
@@ -124,8 +209,11 @@ long long order_hist_entries(long long n);
 int order_max_d();
 hipError_t run_spatial_order(const float *pts, int n, int d, unsigned *keys[2], int *vals[2],
                              int *hist, DevState *st, int **perm, hipStream_t s);
+// With `hoist` (d <= 4, float32 sweep) the staging also writes the rows of
+// the hoisted test for eps2.
 hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float *soa, int *counts,
-                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s);
+                     int *parent, int *jstar, DevState *st, const Order &ord, hipStream_t s,
+                     float *hoist = nullptr, double eps2 = 0.0);
 hipError_t run_count(const Buffers &b, const SweepScalars &sc, bool emit_pairs, hipStream_t s);
 hipError_t run_block_boxes(const float *soa, int n_pad, int d, float *box, hipStream_t s);
 hipError_t run_union(const Buffers &b, const SweepScalars &sc, hipStream_t s);

@@ -35,6 +35,14 @@ __device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevStat
 // Triangular form (each unordered pair tested once); LDS column tallies.
 constexpr int kTriMaxChunk = 4096;
 
+// The hoisted test when its rows were prepared and the input is in its
+// range (hoist_prep_body), else the direct form.
+__device__ __forceinline__ bool use_hoist(const SweepScalars &sc, const DevState *st) {
+  if (!sc.hoist) return false;
+  return !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+           kStatusNoHoist);
+}
+
 template <int D, int R, bool EMIT, bool PRUNE>
 __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa,
                                                    int *__restrict__ counts,
@@ -44,7 +52,11 @@ __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa
   __shared__ int colcnt[kTriMaxChunk];
   __shared__ unsigned long long xfer[5];
   if (skip_sweep(sc, st)) return;
-  count_tri_body<D, R, EMIT, PRUNE>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
+  if (use_hoist(sc, st))
+    count_tri_body<D, R, EMIT, PRUNE, kListQueue, true>(soa, counts, pairs, st, sc, blockIdx.x,
+                                                        qbuf, colcnt, xfer);
+  else
+    count_tri_body<D, R, EMIT, PRUNE>(soa, counts, pairs, st, sc, blockIdx.x, qbuf, colcnt, xfer);
 }
 
 // Pruned form: a persistent grid over the blocks within reach.  Its tiles
@@ -62,10 +74,16 @@ __global__ __launch_bounds__(256) void k_count_tri_pruned(const float *__restric
   __shared__ int colcnt[kTriMaxChunk];
   __shared__ unsigned long long xfer[5];
   if (skip_sweep(sc, st)) return;
-  for_near_blocks<D>(sc, sc.n, [&](int bid) {
-    count_tri_body<D, R, EMIT, true, kPrunedQueue>(soa, counts, pairs, st, sc, bid, qbuf, colcnt,
-                                                   xfer);
-  });
+  if (use_hoist(sc, st))
+    for_near_blocks<D>(sc, sc.n, [&](int bid) {
+      count_tri_body<D, R, EMIT, true, kPrunedQueue, true>(soa, counts, pairs, st, sc, bid, qbuf,
+                                                           colcnt, xfer);
+    });
+  else
+    for_near_blocks<D>(sc, sc.n, [&](int bid) {
+      count_tri_body<D, R, EMIT, true, kPrunedQueue>(soa, counts, pairs, st, sc, bid, qbuf,
+                                                     colcnt, xfer);
+    });
 }
 
 // Boxes of the row groups and of the column chunks of a pruned sweep, each

@@ -112,11 +112,14 @@ def test_workspace_size_layout():
     # 32 x 64 tile, plus O(n) sections
     tri = 4 * (n_pad * n_pad // 64 + n_pad) + n_pad * n_pad // 2048
     assert tri <= out.value < tri + 64 * n_pad
-    # on the fly: O(n d) plus the pair list (8 bytes per pair, 128 pairs per point by default)
+    # on the fly: O(n d) plus the pair list (8 bytes per pair, 128 pairs per
+    # point by default); O(n d) includes the rows of the hoisted test, (d + 2)
+    # floats per row plus per-block origins, boxes and group thresholds
     fly = _lib.make_opts("onthefly")
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(fly), ctypes.byref(out)) == 0
     base = out.value - 8 * 128 * 2_000_000
-    assert 0 < base < 64 * 2_000_128
+    hoist = 4 * (5 * 2_000_128 + 9 * 2_000_128 // 16 + 2_000_128 // 8)
+    assert hoist < base < hoist + 64 * 2_000_128
     auto = _lib.make_opts("auto")  # picks on the fly: the bitmask would be 500 GB
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(auto), ctypes.byref(out)) == 0
     assert out.value == base + 8 * 128 * 2_000_000
@@ -272,6 +275,109 @@ def test_band_sound_on_adversarial_pairs():
             assert exact > e2 * (1 - Fraction(1, 2 ** 50))
             checked += 1
     assert checked > 1000
+
+
+def _f32_round(q):
+    """The float32 nearest to the rational q (ties to even)."""
+    f = np.float32(float(q))
+    best = None
+    for c in (np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))):
+        if not np.isfinite(c):
+            continue
+        key = (abs(Fraction(float(c)) - q), int(np.float32(c).view(np.uint32)) & 1)
+        if best is None or key < best[0]:
+            best = (key, np.float32(c))
+    return best[1]
+
+
+def _fma32(a, b, c):
+    return _f32_round(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def _hoist_band(T, d, eps2):
+    L = _lib.load()
+    lo, hi = ctypes.c_float(), ctypes.c_float()
+    assert L.dbscan_hoist_band(T, d, eps2, ctypes.byref(lo), ctypes.byref(hi)) == 0
+    return np.float32(lo.value), np.float32(hi.value)
+
+
+def _s64(x, y):
+    """The float64 value of the definition: sequential, unfused."""
+    s = 0.0
+    for xk, yk in zip(x, y):
+        t = float(xk) - float(yk)
+        s = s + t * t
+    return s
+
+
+def test_hoist_band_sound_on_adversarial_pairs():
+    """The hoisted test as the on-the-fly sweep evaluates it -- a 16-row
+    block's origin c at the centre of its box, a = fl(x - c), b = fl(y - c),
+    q = fl(|b|^2 - 2a.b) in float32 with fused multiply-adds (emulated with
+    exact rounding) -- against the float64 value of the definition for
+    columns a few ulps from eps away: q <= lo is always a neighbour and
+    q > hi never, at offsets from 0 to 1e6, row spreads from 0.01 eps to
+    100 eps, and eps down to 1e-30 (gradual underflow)."""
+    rng = np.random.default_rng(3)
+    sure_in = sure_out = band = 0
+    for it in range(1200):
+        d = int(rng.integers(1, 5))
+        eps = float(rng.choice([0.25, 0.4, 1.0, 6.0, 1e-3, 1e-30]))
+        eps2 = eps * eps
+        off = float(rng.choice([0.0, 1.0, 500.0, 1e4, 1e6])) if eps > 1e-20 else 0.0
+        spread = eps * float(rng.choice([0.01, 1.0, 10.0, 100.0]))
+        rows = (off + spread * rng.standard_normal((16, d))).astype(np.float32)
+        lo_b, hi_b = rows.min(axis=0), rows.max(axis=0)
+        c = (np.float32(0.5) * lo_b + np.float32(0.5) * hi_b).astype(np.float32)
+        for r in rng.choice(16, size=2, replace=False):
+            x = rows[r]
+            a = (x - c).astype(np.float32)
+            at = (np.float32(-2) * a).astype(np.float32)
+            T = 0.0
+            for ak in a:
+                T += float(ak) * float(ak)
+            lo, hi = _hoist_band(T, d, eps2)
+            v = rng.standard_normal(d)
+            v /= np.linalg.norm(v)
+            y = (x.astype(np.float64) + eps * v).astype(np.float32)
+            y[0] = y[0] + np.float32(rng.integers(-3, 4)) * np.spacing(y[0])
+            b = (y - c).astype(np.float32)
+            P = np.float32(b[0] * b[0])
+            for k in range(1, d):
+                P = _fma32(b[k], b[k], P)
+            q = P
+            for k in range(d):
+                q = _fma32(at[k], b[k], q)
+            s64 = _s64(x, y)
+            if q <= lo:
+                assert s64 <= eps2, (d, eps, off, spread)
+                sure_in += 1
+            elif q > hi:
+                assert s64 > eps2, (d, eps, off, spread)
+                sure_out += 1
+            else:
+                band += 1
+    assert sure_in > 300 and sure_out > 300
+
+
+def test_hoist_band_is_narrow_near_the_origin():
+    """Rows within a few eps of their origin (the blocks of a spatial order)
+    get a band about eps^2 - |a|^2 a few float32 ulps of (r + eps)(3r + eps)
+    wide (r = |a|)."""
+    for eps in (0.25, 0.4, 1.0, 6.0):
+        for d in (1, 2, 3, 4):
+            for r in (0.0, 0.5 * eps, 3 * eps):
+                T = r * r
+                lo, hi = _hoist_band(T, d, eps * eps)
+                assert lo < eps * eps - T < hi
+                assert hi - lo < 4e-6 * (r + eps) * (3 * r + eps)
+    lo, hi = _hoist_band(1.0, 3, 1e-30)
+    assert lo == -np.inf  # eps far below the row's offset: never surely in
+    lo, hi = _hoist_band(0.0, 2, 0.0)
+    assert lo < 0.0 < hi  # eps = 0: a duplicate (q = 0) is settled in float64
+    lo, hi = _hoist_band(1.0, 2, 0.0)
+    assert lo == -np.inf and hi > -1.0
+    assert _hoist_band(4.0, 3, math.inf) == (np.inf, np.inf)
 
 
 def test_server_entry_points_reject_bad_arguments():
