@@ -233,12 +233,15 @@ def serve_bench(args) -> int:
             sts = [srv.wait(i, timeout=600) for i in ids]
             stats = srv.stats()
         lat = np.array([(s["t_done_ns"] - s["t_submit_ns"]) * 1e-6 for s in sts])
+        wait = np.array([(s["t_admit_ns"] - s["t_submit_ns"]) * 1e-6 for s in sts])
+        route = np.array([s["fallback"] for s in sts])  # 1: a worker stream, 0: the loop
         t_first = min(s["t_submit_ns"] for s in sts)
         t_last = max(s["t_done_ns"] for s in sts)
         span = (t_last - t_first) * 1e-9
         bad = sum(1 for s in sts if s["state"] != pkg._lib.JOB_DONE or s["error"] != 0)
         return {"span_s": span, "jobs_per_s": len(jobs) / span, "lat_ms": lat, "stats": stats,
-                "failed": bad, "fallback": sum(s["fallback"] for s in sts)}
+                "failed": bad, "fallback": sum(s["fallback"] for s in sts), "wait_ms": wait,
+                "route": route}
 
     def sequential(pruned):
         """The same jobs one by one through dbscan_fit, enqueued back to back
@@ -278,6 +281,18 @@ def serve_bench(args) -> int:
             mismatches += int(not torch.equal(a, b))
     del seq_outs
     lat = opened["lat_ms"]
+
+    def split(r):
+        """p50/p99 latency and admission wait of the loop's and the workers' jobs."""
+        out = {}
+        for name, sel in (("loop", r["route"] == 0), ("workers", r["route"] == 1)):
+            if sel.any():
+                out[name] = {"jobs": int(sel.sum()),
+                             "p50_ms": round(float(np.percentile(r["lat_ms"][sel], 50)), 3),
+                             "p99_ms": round(float(np.percentile(r["lat_ms"][sel], 99)), 3),
+                             "wait_p99_ms": round(float(np.percentile(r["wait_ms"][sel], 99)), 3)}
+        return out
+
     rec = {
         "metric": "served jobs: p50/p99 latency, jobs/s",
         "value": round(opened["jobs_per_s"], 2),
@@ -294,6 +309,8 @@ def serve_bench(args) -> int:
         "saturation_jobs_per_s": round(closed["jobs_per_s"], 2),
         "closed_loop_p50_ms": round(float(np.percentile(closed["lat_ms"], 50)), 3),
         "closed_loop_p99_ms": round(float(np.percentile(closed["lat_ms"], 99)), 3),
+        "by_route": split(opened),
+        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES", "default"),
         "points_per_s": round(n_tot / opened["span_s"], 1),
         "gpairs_per_s_saturated": round(pairs_tot / closed["span_s"] / 1e9, 3),
         "epochs": int(opened["stats"]["epochs"]),

@@ -259,7 +259,7 @@ int dbscan_hoist_band(double sq_norm, int32_t d, double eps2, float *lo, float *
  * and jobs that arrive while others run are admitted at the next epoch.
  * Every other job (larger n, other d, a precision the loop does not run, or
  * a small job whose lists overflowed) runs the dbscan_fit_ex path on one of
- * six worker streams (float32 jobs with d <= 4 in the spatial order with
+ * eight worker streams (float32 jobs with d <= 4 in the spatial order with
  * tile pruning), with its workspace taken from the same arena, so its
  * kernels overlap with the epochs and with the other workers' jobs.  Each
  * job's outputs equal those of dbscan_fit on the same inputs.  All entry
