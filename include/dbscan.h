@@ -161,8 +161,8 @@ typedef struct dbscan_stats {
   int32_t order_used;     /* DBSCAN_ORDER_INPUT or DBSCAN_ORDER_SPATIAL */
   int32_t pruned;         /* 1 if tile pruning was on (dbscan_opts.prune) */
   int32_t hoisted;        /* 1 if the float32 sweep tested the hoisted form
-                             (on the fly, d <= 4; dbscan_hoist_band), 0 for
-                             the direct form */
+                             (d <= 4, rows in spatial order;
+                             dbscan_hoist_band), 0 for the direct form */
   int32_t reserved0;
 } dbscan_stats;
 

@@ -48,7 +48,12 @@ constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 // apart than eps (box_gap2 > hi) are skipped and left flagged empty (a wave
 // tests the 64 column boxes of its chunk at once, one per lane, and visits
 // only the blocks within reach); the tests actually made go to st->tests.
-template <int D, bool PRUNE>
+//
+// HOIST (sc.hoist): the hoisted test of count_tri_body, each 16-row half of
+// the wave's rows about its own origin (two column preparations per tile).
+// The origins and the group thresholds stay in scalar registers, which keeps
+// the kernel within four waves per SIMD.
+template <int D, bool PRUNE, bool HOIST = false>
 __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
                                              uint32_t *__restrict__ adj,
                                              uint8_t *__restrict__ tflag,
@@ -77,6 +82,8 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     wave_box<D>(lbl, lbh, clo, chi);
     if (box_gap2<D>(rlo, rhi, clo, chi) > sc.hi) return;
   }
+  HoistView<const float> hv{};
+  if (HOIST) hv = hoist_view(sc.hoist, sc.n_pad, D);
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
   if (PRUNE)  // tiles a wave does not visit stay empty
     for (int t = threadIdx.x; t < (kBitmaskMaxRows / 32) * (kBitmaskMaxChunk / 64); t += 256)
@@ -87,11 +94,25 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
     if (cs >= c1) continue;  // wave-uniform
+    // the rows: coordinates (direct form) or -2 fl(x - c) (HOIST)
     float xr[R][D];
+    const float *rows = HOIST ? hv.a : soa;
 #pragma unroll
     for (int r = 0; r < R; ++r)
 #pragma unroll
-      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(soa[(size_t)k * sc.n_pad + row0 + r]);
+      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(rows[(size_t)k * sc.n_pad + row0 + r]);
+    float cen[2][D];     // HOIST: the origins of the two 16-row halves
+    float gate[R / G];   // largest "out" threshold of each group
+#pragma unroll
+    for (int g = 0; g < R / G; ++g) gate[g] = sc.hi;
+    if (HOIST) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < D; ++k) cen[h][k] = hv.cen[(size_t)k * (sc.n_pad / 16) + row0 / 16 + h];
+#pragma unroll
+      for (int g = 0; g < R / G; ++g) gate[g] = hv.hg[row0 / G + g];
+    }
     // two rows' counts per scalar register (a chunk has at most 4096 columns)
     uint32_t cnt2[R / 2];
 #pragma unroll
@@ -99,7 +120,16 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     uint32_t *out = adj + adj_block_base(row0 / R, sc.n_pad);  // indexed by column, from diag
     uint8_t *flag = tiles[(row0 - g0) / R];  // [column block - c0 / 64]
     float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
-    if (PRUNE) {
+    if (PRUNE && HOIST) {
+      const size_t nb16 = sc.n_pad / 16;
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        rlo[k] = __builtin_fminf(hv.box[(2 * k) * nb16 + row0 / 16],
+                                 hv.box[(2 * k) * nb16 + row0 / 16 + 1]);
+        rhi[k] = __builtin_fmaxf(hv.box[(2 * k + 1) * nb16 + row0 / 16],
+                                 hv.box[(2 * k + 1) * nb16 + row0 / 16 + 1]);
+      }
+    } else if (PRUNE) {
 #pragma unroll
       for (int k = 0; k < D; ++k) {
         rlo[k] = xr[0][k];
@@ -114,22 +144,43 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     // the tests of the R rows against the 64 columns cb .. cb + 63 (coordinates xc)
     auto tile = [&](int cb, const float (&xc)[D]) {
       uint32_t word = 0;
+      // HOIST: the column about the current half's origin, and its squared
+      // norm (formed again for the second half)
+      float bq[D], pn = 0.0f;
       // rows in groups of G: the common case (no neighbour among the 64
       // columns for any of the G rows) costs one compare of the group's
       // minimum and one branch; the rows' ballots, the lane's bits and the
       // row counts are taken only in the rare case
 #pragma unroll
       for (int g = 0; g < R / G; ++g) {
+        if (HOIST && g % 2 == 0) {  // two 8-row groups per 16-row half
+#pragma unroll
+          for (int k = 0; k < D; ++k) bq[k] = xc[k] - cen[g / 2][k];
+          pn = bq[0] * bq[0];
+#pragma unroll
+          for (int k = 1; k < D; ++k) pn = __builtin_fmaf(bq[k], bq[k], pn);
+        }
         float sg[G];
 #pragma unroll
-        for (int k = 0; k < G; ++k) sg[k] = sq_dist32<D>(xr[g * G + k], xc);
-        if (__ballot(min_of<G>(sg) <= sc.hi) == 0ull) continue;
+        for (int k = 0; k < G; ++k) {
+          if (HOIST) {
+            float q = pn;
+#pragma unroll
+            for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[g * G + k][kk], bq[kk], q);
+            sg[k] = q;
+          } else {
+            sg[k] = sq_dist32<D>(xr[g * G + k], xc);
+          }
+        }
+        if (__ballot(min_of<G>(sg) <= gate[g]) == 0ull) continue;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
           const int r = g * G + k;
-          const uint64_t mk = __ballot(sg[k] <= sc.hi);
+          const float hi_r = HOIST ? hv.hi[row0 + r] : sc.hi;
+          const float lo_r = HOIST ? hv.lo[row0 + r] : sc.lo;
+          const uint64_t mk = __ballot(sg[k] <= hi_r);
           if (mk == 0ull) continue;
-          const uint64_t lo_m = __ballot(sg[k] <= sc.lo);
+          const uint64_t lo_m = __ballot(sg[k] <= lo_r);
           uint64_t in = mk;
           if (lo_m != in)
             in = recheck_band_soa(in & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
@@ -206,15 +257,21 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
   }
 }
 
+// Launch bounds: the hoisted body needs a few more registers than the direct
+// one; bounded like this the kernel keeps four waves per SIMD at d <= 2 and
+// three at d = 3 (the compiler would otherwise lose one wave per SIMD).
 template <int D>
-__global__ __launch_bounds__(256) void k_bitmask(const float *__restrict__ soa,
+__global__ __launch_bounds__(256, D <= 2 ? 4 : (D == 3 ? 3 : 2)) void k_bitmask(const float *__restrict__ soa,
                                                  uint32_t *__restrict__ adj,
                                                  uint8_t *__restrict__ tflag,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
   __shared__ int colcnt[kBitmaskMaxChunk];
   __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];  // non-empty flags
-  bitmask_body<D, false>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
+  if (use_hoist(sc, st))
+    bitmask_body<D, false, true>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
+  else
+    bitmask_body<D, false>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
 }
 
 // Pruned form: a persistent grid over the blocks that survive the coarse
@@ -228,9 +285,14 @@ __global__ __launch_bounds__(256) void k_bitmask_pruned(const float *__restrict_
                                                         SweepScalars sc) {
   __shared__ int colcnt[kBitmaskMaxChunk];
   __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];
-  for_near_blocks<D>(sc, sc.n_pad, [&](int bid) {
-    bitmask_body<D, true>(soa, adj, tflag, counts, st, sc, bid, colcnt, tiles);
-  });
+  if (use_hoist(sc, st))
+    for_near_blocks<D>(sc, sc.n_pad, [&](int bid) {
+      bitmask_body<D, true, true>(soa, adj, tflag, counts, st, sc, bid, colcnt, tiles);
+    });
+  else
+    for_near_blocks<D>(sc, sc.n_pad, [&](int bid) {
+      bitmask_body<D, true>(soa, adj, tflag, counts, st, sc, bid, colcnt, tiles);
+    });
 }
 
 // --------------------------------------------------- merge from the bitmask

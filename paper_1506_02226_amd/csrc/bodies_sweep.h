@@ -16,6 +16,14 @@ __device__ __forceinline__ uint64_t settle_band(uint64_t m, uint64_t in, const f
   return recheck_band<D>(m & ~in, in, a, b, eps2, st);
 }
 
+// The hoisted test when its rows were prepared and the input is in its
+// range (hoist_prep_body), else the direct form.
+__device__ __forceinline__ bool use_hoist(const SweepScalars &sc, const DevState *st) {
+  if (!sc.hoist) return false;
+  return !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
+           kStatusNoHoist);
+}
+
 // ------------------------------------------------------ pruned launches
 // Persistent form of the triangular sweeps with tile pruning: work-group b
 // of the grid takes the (row group, column chunk) blocks b, b + G, b + 2G,

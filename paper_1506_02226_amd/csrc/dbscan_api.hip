@@ -148,8 +148,11 @@ int plan(int64_t n, int32_t d, const dbscan_opts *o, Layout *L) {
   }
   // boxes of the 64-point blocks, then of the row groups and of the chunks
   if (L->prune) L->off_box = take((uint64_t)3 * 2 * d * (L->n_pad / 64) * 4);
-  // the on-the-fly float32 sweep for d <= 4 tests the hoisted form
-  if (!mfma && L->adjacency == DBSCAN_ADJ_ONTHEFLY && d <= 4)
+  // the float32 step-1 sweeps for d <= 4 (on the fly and bitmask) test the
+  // hoisted form when the rows are in spatial order: in the caller's order
+  // 16 consecutive rows lie anywhere, their origin is far from most of them
+  // and a group's gate (its largest threshold) opens on most tiles
+  if (!mfma && d <= 4 && L->order == DBSCAN_ORDER_SPATIAL)
     L->off_hoist = take(dbk::hoist_floats((int)L->n_pad, d) * 4);
   L->total = off;
   return DBSCAN_OK;
@@ -473,6 +476,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   } else if (bitmask) {
     const Tri t = tri_split(npad, 4096);
     dbk::SweepScalars b1 = sc;
+    b1.hoist = hoist;
     b1.nchunks = t.nchunks;
     b1.chunk = t.chunk;
     b1.rgroup = t.rgroup;

@@ -35,14 +35,6 @@ __device__ __forceinline__ bool skip_sweep(const SweepScalars &sc, const DevStat
 // Triangular form (each unordered pair tested once); LDS column tallies.
 constexpr int kTriMaxChunk = 4096;
 
-// The hoisted test when its rows were prepared and the input is in its
-// range (hoist_prep_body), else the direct form.
-__device__ __forceinline__ bool use_hoist(const SweepScalars &sc, const DevState *st) {
-  if (!sc.hoist) return false;
-  return !(__hip_atomic_load(&st->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &
-           kStatusNoHoist);
-}
-
 template <int D, int R, bool EMIT, bool PRUNE>
 __global__ __launch_bounds__(256) void k_count_tri(const float *__restrict__ soa,
                                                    int *__restrict__ counts,

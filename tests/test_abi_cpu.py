@@ -109,9 +109,9 @@ def test_workspace_size_layout():
     n_pad = 200_192
     # the bit matrix keeps each 32-row block's words from its 64-column
     # diagonal block on: n_pad^2 / 64 + n_pad words, plus a flag byte per
-    # 32 x 64 tile, plus O(n) sections
+    # 32 x 64 tile, plus O(n) sections (the hoisted test's rows among them)
     tri = 4 * (n_pad * n_pad // 64 + n_pad) + n_pad * n_pad // 2048
-    assert tri <= out.value < tri + 64 * n_pad
+    assert tri <= out.value < tri + 96 * n_pad
     # on the fly: O(n d) plus the pair list (8 bytes per pair, 128 pairs per
     # point by default); O(n d) includes the rows of the hoisted test, (d + 2)
     # floats per row plus per-block origins, boxes and group thresholds
@@ -147,8 +147,9 @@ def test_order_option_layout():
     """The spatial order (default for d <= 128 from n = 16384 with the bit
     matrix, 32768 on the matrix cores, 65536 otherwise) adds seven
     n_pad-sized int32 arrays (sort keys and values, two of each; inverse
-    permutation; staged-order counts; per-root label minima) and the radix
-    histograms (256 per 2048-key tile); it is refused where it does not apply."""
+    permutation; staged-order counts; per-root label minima), the radix
+    histograms (256 per 2048-key tile) and, for the float32 sweeps at d <= 4,
+    the rows of the hoisted test; it is refused where it does not apply."""
     L = _lib.load()
     out = ctypes.c_uint64()
     n, n_pad = 200_000, 200_192
@@ -163,7 +164,8 @@ def test_order_option_layout():
         return (b + 255) // 256 * 256
 
     hist = 256 * ((n + 2047) // 2048) * 4
-    extra = 7 * r256(n_pad * 4) + r256(hist)
+    hoist = 4 * (4 * n_pad + 6 * (n_pad // 16) + n_pad // 8)  # d = 2
+    extra = 7 * r256(n_pad * 4) + r256(hist) + r256(hoist)
     for adj in ("bitmask", "onthefly"):
         assert size(adjacency=adj, order="spatial") - size(adjacency=adj, order="input") == extra
         assert size(adjacency=adj) == size(adjacency=adj, order="spatial")  # auto
@@ -179,7 +181,7 @@ def test_order_option_layout():
         o = _lib.make_opts("onthefly", "fp16", order=order)
         assert L.dbscan_workspace_size(n, 64, ctypes.byref(o), ctypes.byref(out)) == 0
         sizes[order] = out.value
-    assert sizes["spatial"] - sizes["input"] == extra
+    assert sizes["spatial"] - sizes["input"] == extra - r256(hoist)  # matrix cores: no hoisted rows
     # auto keeps the input order below each form's threshold, and takes the
     # spatial order from it
     for kw, d, below in ((dict(adjacency="bitmask"), 2, 16_383),
