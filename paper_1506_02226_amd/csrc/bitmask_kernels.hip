@@ -41,6 +41,9 @@ namespace dbk {
 // the sc.chunk columns of one chunk; the grid is row groups x chunks, and a
 // block whose columns all lie before its rows has nothing to do.
 constexpr int kBitmaskMaxChunk = 4096;
+// The all-pairs launch stages its chunk's columns in LDS (LDSCOL): at most
+// this many per block, so that the waves read them there instead of from L2.
+constexpr int kBitmaskLdsChunk = 2048;
 constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 
 // PRUNE (rows in spatial order; not the paper's all-pairs sweep, so reported
@@ -53,13 +56,20 @@ constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 // the wave's rows about its own origin (two column preparations per tile).
 // The origins and the group thresholds stay in scalar registers, which keeps
 // the kernel within four waves per SIMD.
-template <int D, bool PRUNE, bool HOIST = false>
+//
+// LDSCOL (sc.chunk <= kBitmaskLdsChunk): the block first copies its chunk's
+// column coordinates to `lcol` ([k][kBitmaskLdsChunk], LDS) and the waves
+// read the columns there.  With the hoisted test the sweep issues a third
+// fewer instructions and the latency of column loads from L2 (fetched one
+// tile ahead) showed.
+template <int D, bool PRUNE, bool HOIST = false, bool LDSCOL = false>
 __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
                                              uint32_t *__restrict__ adj,
                                              uint8_t *__restrict__ tflag,
                                              int *__restrict__ counts, DevState *__restrict__ st,
                                              const SweepScalars &sc, int bid, int *colcnt,
-                                             uint8_t (*tiles)[kBitmaskMaxChunk / 64]) {
+                                             uint8_t (*tiles)[kBitmaskMaxChunk / 64],
+                                             float *lcol = nullptr) {
   constexpr int R = 32, G = 8;
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
@@ -85,6 +95,14 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
   HoistView<const float> hv{};
   if (HOIST) hv = hoist_view(sc.hoist, sc.n_pad, D);
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
+  if (LDSCOL)
+    for (int t = threadIdx.x; t < c1 - c0; t += 256)
+#pragma unroll
+      for (int k = 0; k < D; ++k) lcol[k * kBitmaskLdsChunk + t] = soa[(size_t)k * sc.n_pad + c0 + t];
+  // column coordinate k of column j (j in the chunk)
+  auto col = [&](int k, int j) -> float {
+    return LDSCOL ? lcol[k * kBitmaskLdsChunk + (j - c0)] : soa[(size_t)k * sc.n_pad + j];
+  };
   if (PRUNE)  // tiles a wave does not visit stay empty
     for (int t = threadIdx.x; t < (kBitmaskMaxRows / 32) * (kBitmaskMaxChunk / 64); t += 256)
       tiles[t / (kBitmaskMaxChunk / 64)][t % (kBitmaskMaxChunk / 64)] = 0;
@@ -222,14 +240,14 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+      for (int k = 0; k < D; ++k) xn[k] = col(k, cs + lane);
       for (int cb = cs; cb < c1; cb += 64) {
         float xc[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) xc[k] = xn[k];
         if (cb + 64 < c1) {
 #pragma unroll
-          for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
+          for (int k = 0; k < D; ++k) xn[k] = col(k, cb + 64 + lane);
         }
         tile(cb, xc);
       }
@@ -266,12 +284,15 @@ __global__ __launch_bounds__(256, D <= 2 ? 4 : (D == 3 ? 3 : 2)) void k_bitmask(
                                                  uint8_t *__restrict__ tflag,
                                                  int *__restrict__ counts,
                                                  DevState *__restrict__ st, SweepScalars sc) {
-  __shared__ int colcnt[kBitmaskMaxChunk];
+  __shared__ int colcnt[kBitmaskLdsChunk];
   __shared__ uint8_t tiles[kBitmaskMaxRows / 32][kBitmaskMaxChunk / 64];  // non-empty flags
+  __shared__ float lcol[D * kBitmaskLdsChunk];
   if (use_hoist(sc, st))
-    bitmask_body<D, false, true>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
+    bitmask_body<D, false, true, true>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles,
+                                       lcol);
   else
-    bitmask_body<D, false>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt, tiles);
+    bitmask_body<D, false, false, true>(soa, adj, tflag, counts, st, sc, blockIdx.x, colcnt,
+                                        tiles, lcol);
 }
 
 // Pruned form: a persistent grid over the blocks that survive the coarse
@@ -501,7 +522,9 @@ __global__ __launch_bounds__(256) void k_clear_flags(uint4 *__restrict__ p, long
 
 // ------------------------------------------------------------ host launchers
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
-  if (sc.chunk % 64 != 0 || sc.chunk > kBitmaskMaxChunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0 ||
+  // the all-pairs launch keeps its chunk's columns in LDS
+  const int max_chunk = sc.box ? kBitmaskMaxChunk : kBitmaskLdsChunk;
+  if (sc.chunk % 64 != 0 || sc.chunk > max_chunk || sc.rgroup % 64 != 0 || sc.rgroup <= 0 ||
       sc.rgroup > kBitmaskMaxRows)
     return hipErrorInvalidValue;
   const int groups = (sc.n_pad + sc.rgroup - 1) / sc.rgroup;

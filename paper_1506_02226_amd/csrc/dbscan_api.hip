@@ -474,7 +474,9 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
     f1.flags = dbk::kOnlyOnFilterFail;
     step(dbk::run_count(bufs, f1, false, s));
   } else if (bitmask) {
-    const Tri t = tri_split(npad, 4096);
+    // chunks of 2,048 columns: the all-pairs bitmask kernel keeps a chunk's
+    // columns in LDS (the pruned one reads them from L2, 4,096 at a time)
+    const Tri t = tri_split(npad, L.prune ? 4096 : 2048);
     dbk::SweepScalars b1 = sc;
     b1.hoist = hoist;
     b1.nchunks = t.nchunks;
