@@ -94,23 +94,44 @@ def test_wide_float32(d):
     assert_same(gpu, ref, f"d={d}")
 
 
+@pytest.mark.parametrize("order", ["input", "spatial"])
 @pytest.mark.parametrize("mode", MODES)
-def test_integer_grid_ties(mode):
+def test_integer_grid_ties(mode, order):
     """Every neighbour pair of a unit grid sits exactly at eps: all of them
-    fall in the float32 band and are decided in float64."""
+    fall in the float32 band (direct form in the caller's order, hoisted
+    form in spatial order) and are decided in float64."""
     g = np.stack(np.meshgrid(np.arange(40), np.arange(30)), -1).reshape(-1, 2).astype(np.float32)
     rng = np.random.default_rng(5)
     g = g[rng.permutation(len(g))]
     g = np.concatenate([g, g[:100]])  # duplicates
     for eps, minpts in ((1.0, 5), (1.0, 6), (np.sqrt(2.0), 9), (2.0, 13)):
-        gpu = run(g, eps, minpts, adjacency=mode, stats=True)
+        gpu = run(g, eps, minpts, adjacency=mode, order=order, stats=True)
         assert_same(gpu, orc.dbscan(g, eps, minpts), f"eps={eps} minpts={minpts}")
+        assert gpu[3]["hoisted"] == (1 if order == "spatial" else 0)
         if eps == 1.0:
             assert gpu[3]["pairs_rechecked"] > 0
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_degenerate_cases(mode):
+def test_hoisted_form_falls_back_beyond_its_range(mode):
+    """A coordinate beyond 2^60 makes the sweep take the direct form (the
+    hoisted form's products could overflow); near 2^59 it keeps the hoisted
+    form.  Outputs equal the oracle either way."""
+    rng = np.random.default_rng(21)
+    for base, hoisted in ((3.0e18, 0), (5.0e17, 1)):
+        centres = rng.uniform(-1, 1, size=(20, 3)) * base
+        pts = (centres[rng.integers(0, 20, 400)] +
+               rng.standard_normal((400, 3)) * base * 1e-6).astype(np.float32)
+        eps = float(base * 3e-6)
+        ref = orc.dbscan(pts, eps, 4)
+        gpu = run(pts, eps, 4, adjacency=mode, order="spatial", stats=True)
+        assert_same(gpu, ref, f"base={base} {mode}")
+        assert gpu[3]["hoisted"] == hoisted, base
+
+
+@pytest.mark.parametrize("order", ["input", "spatial"])
+@pytest.mark.parametrize("mode", MODES)
+def test_degenerate_cases(mode, order):
     rng = np.random.default_rng(9)
     pts = rng.uniform(0, 5, size=(300, 2)).astype(np.float32)
     same = np.zeros((200, 3), np.float32) + 1.5
@@ -119,8 +140,8 @@ def test_degenerate_cases(mode):
                            (np.float32([[3.0, 4.0]]), 1.0, 1), (np.float32([[3.0, 4.0]]), 1.0, 2)):
         if p.shape[1] > 4 and mode == "bitmask":
             continue
-        assert_same(run(p, eps, minpts, adjacency=mode), orc.dbscan(p, eps, minpts),
-                    f"eps={eps} minpts={minpts} n={len(p)}")
+        assert_same(run(p, eps, minpts, adjacency=mode, order=order), orc.dbscan(p, eps, minpts),
+                    f"eps={eps} minpts={minpts} n={len(p)} {order}")
 
 
 def test_large_coordinates_and_tiny_eps():
@@ -130,7 +151,9 @@ def test_large_coordinates_and_tiny_eps():
     for eps, minpts in ((0.1, 3), (1e-3, 2), (0.0625, 4)):
         ref = orc.dbscan(pts, eps, minpts)
         for mode in MODES:
-            assert_same(run(pts, eps, minpts, adjacency=mode), ref, f"eps={eps} {mode}")
+            for order in ("input", "spatial"):
+                assert_same(run(pts, eps, minpts, adjacency=mode, order=order), ref,
+                            f"eps={eps} {mode} {order}")
 
 
 def test_nonfinite_input_reported():
