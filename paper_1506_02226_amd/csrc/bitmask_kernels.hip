@@ -239,17 +239,22 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
         tile(cb, xc);
       }
     } else {
+      // two tiles per iteration in alternating registers (no copies); the
+      // loads are unconditional, past the chunk's last tile they read it again
+      const int clast = c1 - 64;  // c1 - cs is a multiple of 64
+      float xa[D], xb[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xn[k] = col(k, cs + lane);
-      for (int cb = cs; cb < c1; cb += 64) {
-        float xc[D];
+      for (int k = 0; k < D; ++k) xa[k] = col(k, cs + lane);
+      for (int cb = cs; cb < c1; cb += 128) {
+        const int nb = min(cb + 64, clast);
 #pragma unroll
-        for (int k = 0; k < D; ++k) xc[k] = xn[k];
-        if (cb + 64 < c1) {
+        for (int k = 0; k < D; ++k) xb[k] = col(k, nb + lane);
+        tile(cb, xa);
+        if (cb + 64 >= c1) break;
+        const int na = min(cb + 128, clast);
 #pragma unroll
-          for (int k = 0; k < D; ++k) xn[k] = col(k, cb + 64 + lane);
-        }
-        tile(cb, xc);
+        for (int k = 0; k < D; ++k) xa[k] = col(k, na + lane);
+        tile(cb + 64, xb);
       }
     }
     int mine = 0;

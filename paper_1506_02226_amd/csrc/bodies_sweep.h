@@ -257,17 +257,25 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
         tile(cb, xc);
       }
     } else {
+      // two tiles per iteration in alternating registers: the next tile's
+      // columns load into the other set while one is tested (no copies).
+      // The loads are unconditional (past the chunk's last tile they read
+      // that tile again), so the compiler knows how many are in flight and
+      // waits only for the ones a tile uses.
+      const int clast = c1 - 64;  // c1 - cs is a multiple of 64
+      float xa[D], xb[D];
 #pragma unroll
-      for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cs + lane];
-      for (int cb = cs; cb < c1; cb += 64) {
-        float xc[D];
+      for (int k = 0; k < D; ++k) xa[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+      for (int cb = cs; cb < c1; cb += 128) {
+        const int nb = min(cb + 64, clast);
 #pragma unroll
-        for (int k = 0; k < D; ++k) xc[k] = xn[k];
-        if (cb + 64 < c1) {
+        for (int k = 0; k < D; ++k) xb[k] = soa[(size_t)k * sc.n_pad + nb + lane];
+        tile(cb, xa);
+        if (cb + 64 >= c1) break;
+        const int na = min(cb + 128, clast);
 #pragma unroll
-          for (int k = 0; k < D; ++k) xn[k] = soa[(size_t)k * sc.n_pad + cb + 64 + lane];
-        }
-        tile(cb, xc);
+        for (int k = 0; k < D; ++k) xa[k] = soa[(size_t)k * sc.n_pad + na + lane];
+        tile(cb + 64, xb);
       }
     }
     int mine = 0;
