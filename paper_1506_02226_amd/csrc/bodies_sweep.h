@@ -74,9 +74,9 @@ __device__ __forceinline__ void for_near_blocks(const SweepScalars &sc, int rows
 // the sc.chunk columns of one chunk, and an R-row block of a wave only visits
 // the 64-column blocks from the one holding its own rows onwards, so each
 // unordered pair is tested once.  Counts come from both sides of a test: the
-// row side as ballot popcounts (scalar registers), the column side as a
-// per-lane tally (taken only when a row's ballot is not empty) summed per block in
-// `colcnt` (LDS, sc.chunk entries) and added to counts[] at the end.  In the
+// row side as ballot popcounts (scalar registers), the column side as LDS
+// additions (made only when a row's ballot is not empty) into `colcnt`
+// (sc.chunk entries), added to counts[] at the end.  In the
 // diagonal 64x64 block every row visits all 64 columns itself, so there the
 // column tally is not taken, and only pairs below the diagonal are listed.
 //
@@ -177,7 +177,6 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     // the tests of the R rows against the 64 columns cb .. cb + 63 (coordinates xc)
     auto tile = [&](int cb, const float (&xc)[D]) {
       const bool off = cb != diag;
-      uint32_t tally = 0;
       // HOIST: the column about the rows' origin, and its squared norm
       float bq[D], pn = 0.0f;
       if (HOIST) {
@@ -216,7 +215,8 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
           if (lo_m != m)
             in = recheck_band_soa(m & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
                                   sc.eps2, st);
-          tally += ((in >> lane) & 1ull) ? 1u : 0u;
+          // the column side, into the block's tally (only on this rare path)
+          if (off && ((in >> lane) & 1ull)) atomicAdd(&colcnt[cb - c0 + lane], 1);
           cnt[r] += __popcll(in);
           if (EMIT) {
             if (off) {
@@ -229,7 +229,6 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
           }
         }
       }
-      if (off && tally != 0u) atomicAdd(&colcnt[cb - c0 + lane], (int)tally);
     };
     float xn[D];
     if (PRUNE) {
@@ -263,18 +262,21 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       // that tile again), so the compiler knows how many are in flight and
       // waits only for the ones a tile uses.
       const int clast = c1 - 64;  // c1 - cs is a multiple of 64
+      // a wave-uniform base per tile and the lane as the only per-lane offset
+      auto load = [&](float (&x)[D], int cb) {
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          const float *pk = soa + ((size_t)k * sc.n_pad + (size_t)wave_uniform(cb));
+          x[k] = pk[(unsigned)lane];  // zero-extended: a scalar base plus a 32-bit lane offset
+        }
+      };
       float xa[D], xb[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) xa[k] = soa[(size_t)k * sc.n_pad + cs + lane];
+      load(xa, cs);
       for (int cb = cs; cb < c1; cb += 128) {
-        const int nb = min(cb + 64, clast);
-#pragma unroll
-        for (int k = 0; k < D; ++k) xb[k] = soa[(size_t)k * sc.n_pad + nb + lane];
+        load(xb, min(cb + 64, clast));
         tile(cb, xa);
         if (cb + 64 >= c1) break;
-        const int na = min(cb + 128, clast);
-#pragma unroll
-        for (int k = 0; k < D; ++k) xa[k] = soa[(size_t)k * sc.n_pad + na + lane];
+        load(xa, min(cb + 128, clast));
         tile(cb + 64, xb);
       }
     }
