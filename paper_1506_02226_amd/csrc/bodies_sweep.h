@@ -263,12 +263,16 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       // waits only for the ones a tile uses.
       const int clast = c1 - 64;  // c1 - cs is a multiple of 64
       // a wave-uniform base per tile and the lane as the only per-lane offset
-      auto load = [&](float (&x)[D], int cb) {
+      // scalar bases (coordinate k from column cs) and one 32-bit index
+      const float *base[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) {
-          const float *pk = soa + ((size_t)k * sc.n_pad + (size_t)wave_uniform(cb));
-          x[k] = pk[(unsigned)lane];  // zero-extended: a scalar base plus a 32-bit lane offset
-        }
+      for (int k = 0; k < D; ++k) base[k] = soa + ((size_t)k * sc.n_pad + (size_t)cs);
+      auto load = [&](float (&x)[D], int cb) {
+        // a 32-bit byte offset (a chunk spans at most 4,096 columns)
+        const unsigned off = ((unsigned)(cb - cs) + (unsigned)lane) * 4u;
+#pragma unroll
+        for (int k = 0; k < D; ++k)
+          x[k] = *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base[k]) + off);
       };
       float xa[D], xb[D];
       load(xa, cs);
