@@ -123,7 +123,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
     wave_box<D>(lbl, lbh, clo, chi);
     if (box_gap2<D>(rlo, rhi, clo, chi) > sc.hi) return;
   }
-  static_assert(!HOIST || R == 16, "the hoisted rows come in blocks of 16");
+  static_assert(R == 16, "16 rows per wave: two 8-row groups, one 16-row block of the hoisted rows");
   HoistView<const float> hv{};
   if (HOIST) hv = hoist_view(sc.hoist, sc.n_pad, D);
   for (int t = threadIdx.x; t < sc.chunk; t += 256) colcnt[t] = 0;
@@ -186,22 +186,28 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
 #pragma unroll
         for (int k = 1; k < D; ++k) pn = __builtin_fmaf(bq[k], bq[k], pn);
       }
-      // rows in groups of GR: one compare of their minimum and one branch
-      // per group in the common case; the rows' own ballots only in the rare
+      // every row's value, then one compare of their minimum against the
+      // largest threshold and one branch per tile in the common case (with
+      // 16 rows); the groups' own minima and the rows' ballots only in the
+      // rare case
+      float sv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (HOIST) {
+          float q = pn;
+#pragma unroll
+          for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[r][kk], bq[kk], q);
+          sv[r] = q;
+        } else {
+          sv[r] = sq_dist32<D>(xr[r], xc);
+        }
+      }
+      if (__ballot(min_of<R>(sv) <= __builtin_fmaxf(gate[0], gate[1])) == 0ull) return;
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) {
         float sg[GR];
 #pragma unroll
-        for (int k = 0; k < GR; ++k) {
-          if (HOIST) {
-            float q = pn;
-#pragma unroll
-            for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[g * GR + k][kk], bq[kk], q);
-            sg[k] = q;
-          } else {
-            sg[k] = sq_dist32<D>(xr[g * GR + k], xc);
-          }
-        }
+        for (int k = 0; k < GR; ++k) sg[k] = sv[g * GR + k];
         if (__ballot(min_of<GR>(sg) <= gate[g]) == 0ull) continue;
 #pragma unroll
         for (int k = 0; k < GR; ++k) {

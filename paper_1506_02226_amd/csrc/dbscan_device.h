@@ -153,9 +153,18 @@ __device__ __forceinline__ float sq_dist32(const float (&a)[D], const float (&b)
 // skipped as fminf skips it, and compares false like the value itself.
 template <int G>
 __device__ __forceinline__ float min_of(const float (&v)[G]) {
-  static_assert(G == 4 || G == 8, "group size");
+  static_assert(G == 4 || G == 8 || G == 16, "group size");
   if constexpr (G == 4) {
     return __builtin_fminf(__builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]), v[3]);
+  } else if constexpr (G == 16) {  // eight three-operand minima
+    const float a = __builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]);
+    const float b = __builtin_fminf(__builtin_fminf(v[3], v[4]), v[5]);
+    const float c = __builtin_fminf(__builtin_fminf(v[6], v[7]), v[8]);
+    const float e = __builtin_fminf(__builtin_fminf(v[9], v[10]), v[11]);
+    const float f = __builtin_fminf(__builtin_fminf(v[12], v[13]), v[14]);
+    const float g = __builtin_fminf(__builtin_fminf(a, b), c);
+    const float h = __builtin_fminf(__builtin_fminf(e, f), v[15]);
+    return __builtin_fminf(g, h);
   } else {
     const float a = __builtin_fminf(__builtin_fminf(v[0], v[1]), v[2]);
     const float b = __builtin_fminf(__builtin_fminf(v[3], v[4]), v[5]);
