@@ -207,7 +207,10 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
           cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
         }
       }
-      out[cb + lane] = word;
+      // a 32-bit byte offset from the row block's base (a bit matrix that
+      // fits in memory has n_pad well below 2^30)
+      *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(out) + (unsigned)(cb + lane) * 4u) =
+          word;
       const bool filled = __ballot(word != 0u) != 0ull;
       if (lane == 0) flag[(cb - c0) >> 6] = filled ? 1 : 0;
       if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
