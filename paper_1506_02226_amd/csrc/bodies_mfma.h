@@ -268,14 +268,21 @@ __device__ __forceinline__ void mfma_count_body(const T *__restrict__ a_aug,
   constexpr int kChunks = 32 * 2 * KS;
   constexpr int kPer = (kChunks + 255) / 256;  // chunks per thread (1 or 2)
   float pre_n = 0.0f;  // threads 0..31: the norm of row tid of the fetched tile
+  // scalar bases at the item's first row tile and 32-bit byte offsets (an
+  // item spans at most 256 row tiles: 1 MB of a-rows at K = 64), so that the
+  // loads take a scalar base and one 32-bit vector offset
+  const char *a_base = reinterpret_cast<const char *>(a_aug) + (size_t)rt0 * 32 * K * sizeof(T);
+  const char *n_base = reinterpret_cast<const char *>(norms) + (size_t)rt0 * 32 * sizeof(float);
   auto fetch = [&](V(&pre)[kPer], int rt) {
-    const V *src = (const V *)(a_aug + (size_t)rt * 32 * K);
+    const unsigned trel = (unsigned)(rt - rt0);
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = tid + 256 * u;
-      pre[u] = src[e < kChunks ? e : kChunks - 1];  // unconditional: no branch
+      const unsigned off =
+          (trel * 32u * K + (unsigned)(e < kChunks ? e : kChunks - 1) * 8u) * (unsigned)sizeof(T);
+      pre[u] = *reinterpret_cast<const V *>(a_base + off);  // unconditional: no branch
     }
-    pre_n = norms[rt * 32 + (tid & 31)];
+    pre_n = *reinterpret_cast<const float *>(n_base + (trel * 32u + (unsigned)(tid & 31)) * 4u);
   };
   auto stash = [&](const V(&pre)[kPer], int buf) {
 #pragma unroll
