@@ -169,6 +169,9 @@ def test_order_option_layout():
     for adj in ("bitmask", "onthefly"):
         assert size(adjacency=adj, order="spatial") - size(adjacency=adj, order="input") == extra
         assert size(adjacency=adj) == size(adjacency=adj, order="spatial")  # auto
+        # the pruned sweeps test the direct form: no hoisted rows
+        assert (size(adjacency=adj, order="spatial", prune=True)
+                - size(adjacency=adj, order="input", prune=True)) == extra - r256(hoist)
     # d > 4 (pivot order, one radix pass) up to d = 128, matrix cores included
     for d in (5, 128):
         o = _lib.make_opts("onthefly", "fp32", order="spatial")

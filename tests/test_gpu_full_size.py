@@ -47,6 +47,8 @@ def test_blobs2d_200k(form):
     st = out[3]
     assert st["adjacency_used"] == form["adjacency"] and st["order_used"] == form["order"]
     assert st["pruned"] == int(form["prune"])
+    # the hoisted test runs in spatial order; the pruned sweep keeps the direct form
+    assert st["hoisted"] == int(form["order"] == "spatial" and not form["prune"])
     assert_golden(golden("blobs2d_200k"), w.points, out, str(form))
 
 
@@ -69,6 +71,7 @@ def test_aniso3d_2m(form):
     out = _run(x, w.eps, w.minpts, **form)
     st = out[3]
     assert st["adjacency_used"] == "onthefly" and st["order_used"] == form["order"]
+    assert st["hoisted"] == int(form["order"] == "spatial" and not form["prune"])
     assert_golden(golden("aniso3d_2m"), w.points, out, str(form))
 
 
