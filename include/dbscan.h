@@ -250,6 +250,21 @@ int dbscan_fp32_band(double eps2, int32_t d, float *lo, float *hi);
  */
 int dbscan_hoist_band(double sq_norm, int32_t d, double eps2, float *lo, float *hi);
 
+/*
+ * dbscan_hoist_gate -- the gate of one 16-row block of that hoisted test
+ * (Section IV-B.2's form, evaluated as the sweep does).  Per column the
+ * sweep forms, for each row, s = fl(-2 a.b) (a product, then d - 1 fused
+ * multiply-adds) and skips the column for the whole block when
+ * fl(min over rows of s + P) > *gate, P = fl(|b|^2); only otherwise are the
+ * rows' q compared with their thresholds.  hi_max: the largest *hi of the
+ * block's rows (dbscan_hoist_band), sq_norm_max: the largest |a|^2 of its
+ * rows (float64).  The gate is sound: a column with q <= hi for some row of
+ * the block is never skipped.  NaN hi_max (no rows) gives NaN, +inf gives
+ * +inf.  d in 1..4; gate: HOST float*.  DBSCAN_E_INVAL for a null pointer,
+ * d out of range, a negative or NaN sq_norm_max, or hi_max = -inf.
+ */
+int dbscan_hoist_gate(float hi_max, double sq_norm_max, int32_t d, float *gate);
+
 /* ------------------------------------------------------------------ serving
  * A server runs the jobs of many callers on one GPU.  Small jobs (n up to
  * 16,384; float32 for d <= 4, FP16 matrix cores for 16 <= d <= 76) share one

@@ -38,6 +38,7 @@ EXPORTS = (
     "dbscan_version",
     "dbscan_fp32_band",
     "dbscan_hoist_band",
+    "dbscan_hoist_gate",
     "dbscan_server_create",
     "dbscan_batch_submit",
     "dbscan_batch_poll",
@@ -197,6 +198,8 @@ def load(path: str | None = None):
     L.dbscan_hoist_band.argtypes = [dbl, i32, dbl, ctypes.POINTER(ctypes.c_float),
                                     ctypes.POINTER(ctypes.c_float)]
     L.dbscan_hoist_band.restype = ctypes.c_int
+    L.dbscan_hoist_gate.argtypes = [ctypes.c_float, dbl, i32, ctypes.POINTER(ctypes.c_float)]
+    L.dbscan_hoist_gate.restype = ctypes.c_int
     sp = ctypes.c_void_p
     L.dbscan_server_create.argtypes = [ctypes.c_int, ctypes.c_uint64, i32, ctypes.POINTER(sp)]
     L.dbscan_server_create.restype = ctypes.c_int

@@ -73,6 +73,12 @@ __device__ __forceinline__ void hoist_prep_body(const float *__restrict__ soa, i
   float h = hi;
   for (int off = 1; off < 8; off <<= 1) h = __builtin_fmaxf(h, __shfl_xor(h, off));
   if ((i & 7) == 0) v.hg[i >> 3] = h;
+  // the 16-row block's gate: its largest hi and largest |fl(x - c)|^2
+  // (padding rows are NaN and drop out of both maxima)
+  h = __builtin_fmaxf(h, __shfl_xor(h, 8));
+  double t2 = T;
+  for (int off = 1; off < 16; off <<= 1) t2 = __builtin_fmax(t2, __shfl_xor(t2, off));
+  if ((i & 15) == 0) v.g16[blk] = hoist_gate(h, t2, d);
   if (__ballot(far) != 0ull && lane_id() == 0) atomicOr(&st->status, kStatusNoHoist);
 }
 

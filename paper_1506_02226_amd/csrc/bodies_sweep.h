@@ -90,11 +90,15 @@ __device__ __forceinline__ void for_near_blocks(const SweepScalars &sc, int rows
 //
 // HOIST (sc.hoist, rows prepared by hoist_prep_body): the hoisted form of
 // Section IV-B.2 about the origin c of the wave's 16 rows.  Per 64-column
-// tile the wave forms b = fl(y - c) and P = |b|^2 once; per pair it adds
-// the row's -2a.b to P (d fused multiply-adds) and compares the result q
-// with the row's thresholds: q <= lo in, q > hi out, else float64 -- the
-// same decisions as the direct form at about half its instructions.  An
-// 8-row group is skipped when its smallest q exceeds the group's largest hi.
+// tile the wave forms b = fl(y - c) and P = |b|^2 once; per pair it forms
+// s = -2a.b (a product and d - 1 fused multiply-adds, no term from the
+// column, so the product issues at the two-operand rate), and the tile is
+// skipped when fl(min s + P) exceeds the block's gate (hoist_gate: sound for
+// every pair the thresholds could let in).  Otherwise each row's
+// q = fl(P - 2a.b) (d fused multiply-adds from P) is compared with the row's
+// thresholds: q <= lo in, q > hi out, else float64 -- the same decisions as
+// the direct form at about half its instructions.  An 8-row group is
+// skipped when its smallest q exceeds the group's largest hi.
 template <int D, int R, bool EMIT, bool PRUNE = false, int QN = kListQueue, bool HOIST = false>
 __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
                                                int *__restrict__ counts,
@@ -144,6 +148,7 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(rows[(size_t)k * sc.n_pad + row0 + r]);
     float cen[D];         // HOIST: the rows' origin
     float gate[R / GR];   // largest "out" threshold of each group
+    float gate16 = sc.hi; // the 16 rows' gate (HOIST: hoist_gate, on min s + P)
 #pragma unroll
     for (int g = 0; g < R / GR; ++g) gate[g] = sc.hi;
     if (HOIST) {
@@ -151,6 +156,9 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       for (int k = 0; k < D; ++k) cen[k] = to_vgpr(hv.cen[(size_t)k * (sc.n_pad / 16) + row0 / 16]);
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) gate[g] = to_vgpr(hv.hg[row0 / GR + g]);
+      gate16 = to_vgpr(hv.g16[row0 / 16]);
+    } else {
+      gate16 = __builtin_fmaxf(gate[0], gate[1]);
     }
     int cnt[R];
 #pragma unroll
@@ -191,18 +199,28 @@ __device__ __forceinline__ void count_tri_body(const float *__restrict__ soa,
       // 16 rows); the groups' own minima and the rows' ballots only in the
       // rare case
       float sv[R];
+      if (HOIST) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (HOIST) {
+        for (int r = 0; r < R; ++r) {
+          float s = xr[r][0] * bq[0];
+#pragma unroll
+          for (int kk = 1; kk < D; ++kk) s = __builtin_fmaf(xr[r][kk], bq[kk], s);
+          sv[r] = s;
+        }
+        if (__ballot(min_of<R>(sv) + pn <= gate16) == 0ull) return;
+        // the rows' values as the thresholds were derived for
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
           float q = pn;
 #pragma unroll
           for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[r][kk], bq[kk], q);
           sv[r] = q;
-        } else {
-          sv[r] = sq_dist32<D>(xr[r], xc);
         }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) sv[r] = sq_dist32<D>(xr[r], xc);
+        if (__ballot(min_of<R>(sv) <= gate16) == 0ull) return;
       }
-      if (__ballot(min_of<R>(sv) <= __builtin_fmaxf(gate[0], gate[1])) == 0ull) return;
 #pragma unroll
       for (int g = 0; g < R / GR; ++g) {
         float sg[GR];

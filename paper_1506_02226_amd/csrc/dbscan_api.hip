@@ -306,6 +306,13 @@ int dbscan_hoist_band(double sq_norm, int32_t d, double eps2, float *lo, float *
   return DBSCAN_OK;
 }
 
+int dbscan_hoist_gate(float hi_max, double sq_norm_max, int32_t d, float *gate) {
+  if (!gate || d < 1 || d > 4 || !(sq_norm_max >= 0.0) || hi_max == -__builtin_inff())
+    return DBSCAN_E_INVAL;
+  *gate = dbk::hoist_gate(hi_max, sq_norm_max, d);
+  return DBSCAN_OK;
+}
+
 const char *dbscan_strerror(int code) {
   switch (code) {
     case DBSCAN_OK: return "ok";

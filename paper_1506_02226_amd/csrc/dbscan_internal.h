@@ -57,8 +57,9 @@ struct SweepScalars {
 // of the staged order has an origin c (the centre of its box), and row i
 // keeps a = -2 fl(x_i - c) and its float32 thresholds (hoist_prep_body).
 // Layout (floats): a [k][n_pad], lo [n_pad], hi [n_pad], the blocks' boxes
-// [2k][n_pad/16] (lo, hi), their origins [k][n_pad/16], and per 8-row group
-// the largest hi [n_pad/8].
+// [2k][n_pad/16] (lo, hi), their origins [k][n_pad/16], per 8-row group
+// the largest hi [n_pad/8], and per 16-row block its gate [n_pad/16]
+// (hoist_gate).
 // The float32 value next to finite x, upwards (dir = 1) or downwards (-1).
 __host__ __device__ inline float f32_step(float x, int dir) {
   if (x == 0.0f) return dir > 0 ? 1.40129846e-45f : -1.40129846e-45f;
@@ -117,12 +118,49 @@ __host__ __device__ inline void hoist_band(double T, int d, double eps2, float *
   *lo = lf;
 }
 
+// Gate of a 16-row block of the hoisted test.  Per column the sweep forms,
+// for each row r of the block, s_r = fl(a'_r . b) with a'_r = -2 fl(x_r - c)
+// (a product, then d - 1 fused multiply-adds), and compares fl(min_r s_r + P)
+// once with the block's gate (P = the column's float32 |b|^2); only when that
+// passes does it form the rows' values q_r = fl(P + a'_r . b) (d fused
+// multiply-adds from P) and test them against their thresholds.  The gate
+// must pass every column with q_r <= hi_r for some row.  With g = gamma_d,
+// E_r = P + a'_r . b exact, S_r = sum_k |a'_rk b_k| <= 2 rho |b| (rho >= every
+// |fl(x_r - c)| of the block) and e an allowance for gradual underflow:
+//   |q_r - E_r| <= g (P + S_r) + e,  |s_r - a'_r . b| <= g S_r + e,
+//   |P - |b|^2| <= g |b|^2 + e.
+// If q_r <= hi_r <= H (H the block's largest hi), then
+// (1 - g) |b|^2 - 2 rho |b| - e <= E_r <= H + g (P + 2 rho |b|) + e bounds |b|
+// by B, the positive root of (1 - 2g - g^2) z^2 - 2 rho (1 + g) z - H+ = 0
+// (H+ = max(H, 0) plus the underflow terms), and
+//   min_r s_r + P <= s_r + P <= H + g ((1 + g) B^2 + 4 rho B) + 3e.
+// Rounding is monotone, so fl(min_r s_r + P) is at most that bound rounded
+// up, which is the gate.  A NaN H (every row padding) gives a NaN gate, which
+// no column passes; H = +inf (eps = inf) gives +inf.
+__host__ __device__ inline float hoist_gate(float H, double rho2, int d) {
+  if (!(H == H) || __builtin_isinf(H)) return H;
+  const double u = 0x1p-24;
+  const double g = (d * u / (1.0 - d * u)) * (1.0 + 0x1p-40);
+  const double e = 8.0 * d * 0x1p-149;
+  const double rho = __builtin_sqrt(rho2) * (1.0 + 0x1p-48);
+  const double Hp = ((double)H > 0.0 ? (double)H : 0.0) + 4.0 * e;
+  const double al = 1.0 - 2.0 * g - g * g;
+  const double be = rho * (1.0 + g);
+  const double B = (be + __builtin_sqrt(be * be + al * Hp)) / al * (1.0 + 0x1p-48);
+  const double S = g * ((1.0 + g) * B * B + 4.0 * rho * B) + 3.0 * e;
+  double G = (double)H + S;
+  G += 0x1p-48 * (__builtin_fabs((double)H) + S);
+  float gf = (float)G;
+  if ((double)gf < G) gf = f32_step(gf, 1);
+  return gf;
+}
+
 template <typename F>
 struct HoistView {
-  F *a, *lo, *hi, *box, *cen, *hg;
+  F *a, *lo, *hi, *box, *cen, *hg, *g16;
 };
 __host__ __device__ inline unsigned long long hoist_floats(int n_pad, int d) {
-  return (unsigned long long)(d + 2) * n_pad + 3ull * d * (n_pad / 16) + n_pad / 8;
+  return (unsigned long long)(d + 2) * n_pad + (3ull * d + 1) * (n_pad / 16) + n_pad / 8;
 }
 template <typename F>
 __host__ __device__ inline HoistView<F> hoist_view(F *base, int n_pad, int d) {
@@ -133,6 +171,7 @@ __host__ __device__ inline HoistView<F> hoist_view(F *base, int n_pad, int d) {
   v.box = v.hi + n_pad;
   v.cen = v.box + (size_t)2 * d * (n_pad / 16);
   v.hg = v.cen + (size_t)d * (n_pad / 16);
+  v.g16 = v.hg + n_pad / 8;
   return v;
 }
 

@@ -118,7 +118,7 @@ def test_workspace_size_layout():
     fly = _lib.make_opts("onthefly")
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(fly), ctypes.byref(out)) == 0
     base = out.value - 8 * 128 * 2_000_000
-    hoist = 4 * (5 * 2_000_128 + 9 * 2_000_128 // 16 + 2_000_128 // 8)
+    hoist = 4 * (5 * 2_000_128 + 10 * 2_000_128 // 16 + 2_000_128 // 8)
     assert hoist < base < hoist + 64 * 2_000_128
     auto = _lib.make_opts("auto")  # picks on the fly: the bitmask would be 500 GB
     assert L.dbscan_workspace_size(2_000_000, 3, ctypes.byref(auto), ctypes.byref(out)) == 0
@@ -164,7 +164,7 @@ def test_order_option_layout():
         return (b + 255) // 256 * 256
 
     hist = 256 * ((n + 2047) // 2048) * 4
-    hoist = 4 * (4 * n_pad + 6 * (n_pad // 16) + n_pad // 8)  # d = 2
+    hoist = 4 * (4 * n_pad + 7 * (n_pad // 16) + n_pad // 8)  # d = 2
     extra = 7 * r256(n_pad * 4) + r256(hist) + r256(hoist)
     for adj in ("bitmask", "onthefly"):
         assert size(adjacency=adj, order="spatial") - size(adjacency=adj, order="input") == extra
@@ -209,7 +209,8 @@ def test_order_option_layout():
 def test_prune_option():
     """Tile pruning: float32 forms with d <= 4 only; it adds the boxes of the
     64-point blocks, row groups and column chunks (3 x 2 d floats per block)
-    to the workspace."""
+    to the workspace, and drops the hoisted test's rows (the pruned sweep
+    tests the direct form)."""
     L = _lib.load()
     out = ctypes.c_uint64()
     sizes = {}
@@ -217,7 +218,9 @@ def test_prune_option():
         o = _lib.make_opts("onthefly", "fp32", prune=prune)
         assert L.dbscan_workspace_size(100_000, 3, ctypes.byref(o), ctypes.byref(out)) == 0
         sizes[prune] = out.value
-    assert sizes[True] - sizes[False] == (3 * 2 * 3 * (100_096 // 64) * 4 + 255) // 256 * 256
+    r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    hoist = 4 * (5 * 100_096 + 10 * (100_096 // 16) + 100_096 // 8)  # d = 3, spatial order
+    assert sizes[True] - sizes[False] == r256(3 * 2 * 3 * (100_096 // 64) * 4) - r256(hoist)
     for d, prec in ((5, "fp32"), (16, "fp16"), (2, "fp16")):
         o = _lib.make_opts("onthefly", prec, prune=True)
         assert L.dbscan_workspace_size(1000, d, ctypes.byref(o), ctypes.byref(out)) == \
@@ -363,6 +366,122 @@ def test_hoist_band_sound_on_adversarial_pairs():
             else:
                 band += 1
     assert sure_in > 300 and sure_out > 300
+
+
+def _hoist_gate(H, rho2, d):
+    L = _lib.load()
+    g = ctypes.c_float()
+    assert L.dbscan_hoist_gate(float(H), float(rho2), d, ctypes.byref(g)) == 0
+    return np.float32(g.value)
+
+
+def test_hoist_gate_sound_on_adversarial_columns():
+    """The 16-row gate of the hoisted test as the on-the-fly sweep evaluates
+    it: per column s_r = fl(-2a_r.b) (a product, then fused multiply-adds),
+    the tile skipped when fl(min_r s_r + P) > gate, with P = fl(|b|^2) and the
+    rows' q_r = fl(P - 2a_r.b) formed only past the gate (all emulated with
+    exact rounding).  Every column that some row's threshold would let in
+    (q_r <= hi_r) must pass the gate.  Columns are placed where q_r crosses
+    hi_r (the worst case for the gate) and at random distances; blocks carry
+    padding rows (NaN) in some trials.  Without its slack the gate would skip
+    some of these columns, so the test reaches the bound it checks."""
+    rng = np.random.default_rng(17)
+    needed_slack = critical = skipped = 0
+    for it in range(160):
+        d = int(rng.integers(1, 5))
+        eps = float(rng.choice([0.25, 0.4, 1.0, 6.0, 1e-3, 1e-30]))
+        eps2 = eps * eps
+        off = float(rng.choice([0.0, 1.0, 500.0, 1e4, 1e6])) if eps > 1e-20 else 0.0
+        spread = eps * float(rng.choice([0.01, 1.0, 10.0, 100.0]))
+        real = 16 - (int(rng.integers(1, 12)) if it % 4 == 3 else 0)
+        rows = (off + spread * rng.standard_normal((real, d))).astype(np.float32)
+        lo_b, hi_b = rows.min(axis=0), rows.max(axis=0)
+        c = (np.float32(0.5) * lo_b + np.float32(0.5) * hi_b).astype(np.float32)
+        a = (rows - c).astype(np.float32)
+        at = (np.float32(-2) * a).astype(np.float32)
+        T = [sum(float(v) * float(v) for v in a[r]) for r in range(real)]
+        his = [_hoist_band(T[r], d, eps2)[1] for r in range(real)]
+        H = np.float32(max(his))
+        gate = _hoist_gate(H, max(T), d)
+        assert gate >= H
+        def norm2(b):
+            P = _f32_round(Fraction(float(b[0])) * Fraction(float(b[0])))
+            for k in range(1, d):
+                P = _fma32(b[k], b[k], P)
+            return P
+
+        def q_of(r, b, P):
+            qr = P
+            for k in range(d):
+                qr = _fma32(at[r][k], b[k], qr)
+            return qr
+
+        cols = []
+        for col in range(6):
+            # where the value of the row with the largest threshold crosses
+            # it: y on a random ray at that distance, then the coordinate-0
+            # steps at which q crosses hi (the worst case for the gate)
+            r0 = int(np.argmax(his)) if col < 4 else int(rng.integers(0, real))
+            v = rng.standard_normal(d)
+            v /= np.linalg.norm(v)
+            t = math.sqrt(max(float(his[r0]) + T[r0], 0.0))
+            y0 = (rows[r0].astype(np.float64) + t * v).astype(np.float32)
+            qs = []
+            for j in range(-48, 49):
+                y = y0.copy()
+                y[0] = y0[0] + np.float32(j) * np.spacing(y0[0])
+                b = (y - c).astype(np.float32)
+                qs.append((y, q_of(r0, b, norm2(b)) <= his[r0]))
+            cols += [qs[j][0] for j in range(len(qs) - 1) if qs[j][1] != qs[j + 1][1]][:2]
+            cols += [qs[j + 1][0] for j in range(len(qs) - 1) if qs[j][1] != qs[j + 1][1]][:2]
+        for col in range(4):  # random distances
+            r0 = int(rng.integers(0, real))
+            v = rng.standard_normal(d)
+            v /= np.linalg.norm(v)
+            cols.append((rows[r0].astype(np.float64) + eps * float(rng.uniform(0.0, 1.5)) * v)
+                        .astype(np.float32))
+        for y in cols:
+            b = (y - c).astype(np.float32)
+            P = norm2(b)
+            q, s = [], []
+            for r in range(real):
+                qr = P
+                for k in range(d):
+                    qr = _fma32(at[r][k], b[k], qr)
+                q.append(qr)
+                sr = _f32_round(Fraction(float(at[r][0])) * Fraction(float(b[0])))
+                for k in range(1, d):
+                    sr = _fma32(at[r][k], b[k], sr)
+                s.append(sr)
+            g = _f32_round(Fraction(float(min(s))) + Fraction(float(P)))
+            if any(q[r] <= his[r] for r in range(real)):
+                critical += 1
+                assert g <= gate, (d, eps, off, spread, real, float(g), float(gate))
+                needed_slack += bool(g > H)
+            else:
+                skipped += bool(g > gate)
+    assert critical > 300 and needed_slack > 0 and skipped > 50
+
+
+def test_hoist_gate_special_values():
+    """NaN (a block of padding) stays NaN, +inf (eps = inf) stays +inf, -inf
+    and bad arguments are refused; near the origin the gate sits a few
+    float32 ulps of (r + eps)^2 above the block's largest threshold."""
+    L = _lib.load()
+    g = ctypes.c_float()
+    assert math.isnan(_hoist_gate(float("nan"), 1.0, 3))
+    assert _hoist_gate(float("inf"), 1.0, 3) == np.inf
+    assert L.dbscan_hoist_gate(float("-inf"), 1.0, 3, ctypes.byref(g)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_hoist_gate(1.0, -1.0, 3, ctypes.byref(g)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_hoist_gate(1.0, 1.0, 5, ctypes.byref(g)) == _lib.DBSCAN_E_INVAL
+    assert L.dbscan_hoist_gate(1.0, 1.0, 3, None) == _lib.DBSCAN_E_INVAL
+    for eps in (0.25, 0.4, 6.0):
+        for d in (1, 2, 3, 4):
+            for r in (0.0, 0.5 * eps, 3 * eps):
+                _, hi = _hoist_band(r * r, d, eps * eps)
+                gate = _hoist_gate(hi, r * r, d)
+                assert hi <= gate <= hi + 4e-6 * (2 * r + eps) ** 2
+    assert _hoist_gate(-5.0, 4.0, 2) >= -5.0
 
 
 def test_hoist_band_is_narrow_near_the_origin():
