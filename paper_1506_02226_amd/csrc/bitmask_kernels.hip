@@ -54,8 +54,10 @@ constexpr int kBitmaskMaxRows = 512;  // rows per block (sc.rgroup) at most
 //
 // HOIST (sc.hoist): the hoisted test of count_tri_body, each 16-row half of
 // the wave's rows about its own origin (two column preparations per tile).
-// The origins and the group thresholds stay in scalar registers, which keeps
-// the kernel within four waves per SIMD.
+// The group thresholds stay in scalar registers (read with readfirstlane, so
+// their loads are waited for before the tile loop, not at the loop's first
+// compare on every iteration, where the wait would also cover the previous
+// tile's word store).
 //
 // LDSCOL (sc.chunk <= kBitmaskLdsChunk): the block first copies its chunk's
 // column coordinates to `lcol` ([k][kBitmaskLdsChunk], LDS) and the waves
@@ -129,8 +131,12 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
 #pragma unroll
         for (int k = 0; k < D; ++k) cen[h][k] = hv.cen[(size_t)k * (sc.n_pad / 16) + row0 / 16 + h];
 #pragma unroll
-      for (int g = 0; g < R / G; ++g) gate[g] = hv.hg[row0 / G + g];
+      for (int g = 0; g < R / G; ++g) gate[g] = wave_uniform_f(hv.hg[row0 / G + g]);
     }
+    float gate16[R / 16];  // the larger threshold of each half's two groups
+#pragma unroll
+    for (int h = 0; h < R / 16; ++h)
+      gate16[h] = wave_uniform_f(__builtin_fmaxf(gate[2 * h], gate[2 * h + 1]));
     // two rows' counts per scalar register (a chunk has at most 4096 columns)
     uint32_t cnt2[R / 2];
 #pragma unroll
@@ -162,49 +168,57 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     // the tests of the R rows against the 64 columns cb .. cb + 63 (coordinates xc)
     auto tile = [&](int cb, const float (&xc)[D]) {
       uint32_t word = 0;
-      // HOIST: the column about the current half's origin, and its squared
-      // norm (formed again for the second half)
-      float bq[D], pn = 0.0f;
-      // rows in groups of G: the common case (no neighbour among the 64
-      // columns for any of the G rows) costs one compare of the group's
-      // minimum and one branch; the rows' ballots, the lane's bits and the
-      // row counts are taken only in the rare case
+      // rows in 16-row halves (HOIST: each about its own origin, so the
+      // column and its squared norm are formed per half): the common case
+      // (no neighbour among the 64 columns for any of the 16 rows) costs one
+      // compare of their minimum with the larger of the halves' two group
+      // thresholds and one branch; the groups' own minima, the rows'
+      // ballots, the lane's bits and the row counts only in the rare case
 #pragma unroll
-      for (int g = 0; g < R / G; ++g) {
-        if (HOIST && g % 2 == 0) {  // two 8-row groups per 16-row half
+      for (int h = 0; h < R / 16; ++h) {
+        float bq[D], pn = 0.0f;
+        if (HOIST) {
 #pragma unroll
-          for (int k = 0; k < D; ++k) bq[k] = xc[k] - cen[g / 2][k];
+          for (int k = 0; k < D; ++k) bq[k] = xc[k] - cen[h][k];
           pn = bq[0] * bq[0];
 #pragma unroll
           for (int k = 1; k < D; ++k) pn = __builtin_fmaf(bq[k], bq[k], pn);
         }
-        float sg[G];
+        float sv[16];
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
+        for (int k = 0; k < 16; ++k) {
           if (HOIST) {
             float q = pn;
 #pragma unroll
-            for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[g * G + k][kk], bq[kk], q);
-            sg[k] = q;
+            for (int kk = 0; kk < D; ++kk) q = __builtin_fmaf(xr[h * 16 + k][kk], bq[kk], q);
+            sv[k] = q;
           } else {
-            sg[k] = sq_dist32<D>(xr[g * G + k], xc);
+            sv[k] = sq_dist32<D>(xr[h * 16 + k], xc);
           }
         }
-        if (__ballot(min_of<G>(sg) <= gate[g]) == 0ull) continue;
+        if (__ballot(min_of<16>(sv) <= gate16[h]) == 0ull) continue;
 #pragma unroll
-        for (int k = 0; k < G; ++k) {
-          const int r = g * G + k;
-          const float hi_r = HOIST ? hv.hi[row0 + r] : sc.hi;
-          const float lo_r = HOIST ? hv.lo[row0 + r] : sc.lo;
-          const uint64_t mk = __ballot(sg[k] <= hi_r);
-          if (mk == 0ull) continue;
-          const uint64_t lo_m = __ballot(sg[k] <= lo_r);
-          uint64_t in = mk;
-          if (lo_m != in)
-            in = recheck_band_soa(in & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
-                                  sc.eps2, st);
-          word |= ((in >> lane) & 1ull) ? (1u << r) : 0u;
-          cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
+        for (int gg = 0; gg < 16 / G; ++gg) {
+          const int g = h * (16 / G) + gg;
+          float sg[G];
+#pragma unroll
+          for (int k = 0; k < G; ++k) sg[k] = sv[gg * G + k];
+          if (__ballot(min_of<G>(sg) <= gate[g]) == 0ull) continue;
+#pragma unroll
+          for (int k = 0; k < G; ++k) {
+            const int r = g * G + k;
+            const float hi_r = HOIST ? hv.hi[row0 + r] : sc.hi;
+            const float lo_r = HOIST ? hv.lo[row0 + r] : sc.lo;
+            const uint64_t mk = __ballot(sg[k] <= hi_r);
+            if (mk == 0ull) continue;
+            const uint64_t lo_m = __ballot(sg[k] <= lo_r);
+            uint64_t in = mk;
+            if (lo_m != in)
+              in = recheck_band_soa(in & ~lo_m, lo_m, soa, sc.n_pad, D, row0 + r, cb + lane,
+                                    sc.eps2, st);
+            word |= ((in >> lane) & 1ull) ? (1u << r) : 0u;
+            cnt2[r >> 1] += (uint32_t)__popcll(in) << ((r & 1) * 16);
+          }
         }
       }
       // a 32-bit byte offset from the row block's base (a bit matrix that

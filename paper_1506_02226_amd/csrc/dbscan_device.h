@@ -55,6 +55,13 @@ constexpr int kNoNeighbour = 0x7fffffff;
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A wave-uniform float in a scalar register.  Its load is waited for here: a
+// value loaded before a loop and first read inside it makes the compiler wait
+// at that read on every iteration, for every memory operation in flight
+// (stores included).
+__device__ __forceinline__ float wave_uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 
 // Neighbouring float32 values (finite x).
 __device__ __forceinline__ float next_down(float x) {
