@@ -341,7 +341,8 @@ __global__ __launch_bounds__(256) void k_bitmask_pruned(const float *__restrict_
 // --------------------------------------------------- merge from the bitmask
 // Step 3 and the border points, from the lower triangle of the bitmask.  The
 // passes read only the 32 x 64 tiles flagged non-empty (64 flags at a time),
-// and one wave owns 64 rows i (lanes).  With rows in spatial order, first:
+// and one wave owns 64 rows i (lanes).  With rows in spatial order, and in
+// the caller's order for at most 16,384 rows (HOOKED), first:
 //
 //  1. k_merge_hook: every core row i hooks under its lowest-index core
 //     neighbour j < i among the 2048 columns below its 64-row block (the
@@ -355,10 +356,12 @@ __global__ __launch_bounds__(256) void k_bitmask_pruned(const float *__restrict_
 //
 //  3. k_merge_bitmask: every neighbour pair (i, j), j < i, once:
 //     * core i, core j: joined in the union-find (queued, drained 64 pairs
-//       at a time).  In spatial order the word's 32 column parents are
-//       loaded too (one per lane): when all its core columns hang under one
-//       parent P -- the common case there -- the word needs no union if P is
-//       i's root and one union otherwise.  (In the caller's order the
+//       at a time).  When hooked, the word's 32 column parents are loaded
+//       too (one per lane): when all its core columns hang under one parent
+//       P -- the common case in spatial order -- the word needs no union if
+//       P is i's root and one union otherwise; in the caller's order, where
+//       a word's columns mix clusters, each pair is skipped when its column's
+//       parent is i's root.  (Without the hook, in the caller's order, the
 //       parents of a word's columns rarely agree and the loads would only
 //       add latency.)
 //     * core i, non-core j: i is a core neighbour of j (atomicMin on
@@ -465,7 +468,7 @@ __global__ void k_merge_compress(int *__restrict__ parent, int n) {
   }
 }
 
-template <bool ORDERED>
+template <bool ORDERED, bool HOOKED>
 __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restrict__ adj,
                                                        const uint8_t *__restrict__ tflag,
                                                        const uint32_t *__restrict__ corebits,
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   bool seek = m.valid && !m.is_core;
   int best = kNoNeighbour;                                 // ORDERED, non-core rows
   const int my_key = (ORDERED && m.valid) ? okey[i] : i;  // key of row i in jstar
-  const int root_i = (ORDERED && m.is_core) ? parent[i] : -1;  // after the compress pass
+  const int root_i = (HOOKED && m.is_core) ? parent[i] : -1;  // after the compress pass
   WaveQueue qu{qbuf[w], 0, 64};
   for_flagged_words(
       adj, m, p.n_pad,
@@ -512,7 +515,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
         // core-core pairs
         uint32_t cc = m.is_core ? (word & cw) : 0u;
         if (__ballot(cc != 0u) == 0ull) return;
-        if (ORDERED) {
+        if (HOOKED) {
           const int pc = parent[q * 32 + (lane & 31)];  // lanes l and l + 32: column l
           const int P = __builtin_amdgcn_readlane(pc, __builtin_ctz(cw));
           if (__ballot(((cw >> (lane & 31)) & 1u) && pc != P) == 0ull) {
@@ -526,7 +529,10 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
           const bool has = cc != 0u;
           const int b = has ? __builtin_ctz(cc) : 0;
           cc &= cc - 1u;
-          wq_push(qu, has, i, q * 32 + b);
+          // hooked, in the caller's order: a column whose parent is i's
+          // root is in i's tree already (its parent is a common ancestor)
+          const bool join = (HOOKED && !ORDERED && has) ? parent[q * 32 + b] != root_i : has;
+          wq_push(qu, join, i, q * 32 + b);
           wq_drain_union(qu, parent, false);
         }
       },
@@ -579,9 +585,19 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
   return hipGetLastError();
 }
 
+// The hook and compress passes run in spatial order, and in the caller's
+// order up to 16,384 rows, where the hook's window (the 2,048 columns below a
+// row's 64-row block) is at least an eighth of each row's lower triangle.
+// Without them every core-core pair there was a union, and the unions of a
+// cluster all contended for its few roots.  Measured per call (whole step):
+// blobs2d_small 0.096 -> 0.074 ms, the same recipe at n = 8,000 0.76 -> 0.43
+// ms, the blobs2d_200k recipe at n = 16,000 0.30 -> 0.18 ms.
+constexpr int kHookCallerOrderMax = 16384;
+
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
-  if (b.okey) {
+  const bool hooked = b.okey || sc.n_pad <= kHookCallerOrderMax;
+  if (hooked) {
     SweepScalars whole = sc;  // the hook pass scans each row's words in one piece
     whole.nchunks = 1;
     whole.chunk = sc.n_pad / 32;
@@ -591,13 +607,17 @@ hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream
                        sc.n);
   }
   if (b.okey)
-    hipLaunchKernelGGL(k_merge_bitmask<true>, dim3(groups * sc.nchunks), dim3(256), 0, s,
+    hipLaunchKernelGGL((k_merge_bitmask<true, true>), dim3(groups * sc.nchunks), dim3(256), 0, s,
                        (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
                        sc);
+  else if (hooked)
+    hipLaunchKernelGGL((k_merge_bitmask<false, true>), dim3(groups * sc.nchunks), dim3(256), 0,
+                       s, (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar,
+                       b.okey, sc);
   else
-    hipLaunchKernelGGL(k_merge_bitmask<false>, dim3(groups * sc.nchunks), dim3(256), 0, s,
-                       (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
-                       sc);
+    hipLaunchKernelGGL((k_merge_bitmask<false, false>), dim3(groups * sc.nchunks), dim3(256), 0,
+                       s, (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar,
+                       b.okey, sc);
   return hipGetLastError();
 }
 
