@@ -143,6 +143,7 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     for (int r = 0; r < R / 2; ++r) cnt2[r] = 0;
     uint32_t *out = adj + adj_block_base(row0 / R, sc.n_pad);  // indexed by column, from diag
     uint8_t *flag = tiles[(row0 - g0) / R];  // [column block - c0 / 64]
+    uint64_t filled = 0;  // bit t: the tile of column block c0 / 64 + t holds a bit
     float rlo[D], rhi[D];  // PRUNE: box of the R rows (padded rows are NaN, skipped)
     if (PRUNE && HOIST) {
       const size_t nb16 = sc.n_pad / 16;
@@ -225,9 +226,13 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
       // fits in memory has n_pad well below 2^30)
       *reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(out) + (unsigned)(cb + lane) * 4u) =
           word;
-      const bool filled = __ballot(word != 0u) != 0ull;
-      if (lane == 0) flag[(cb - c0) >> 6] = filled ? 1 : 0;
-      if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
+      // the tile's flag and column tallies only when it holds a bit (a
+      // wave-uniform branch: no LDS operation in the common case, so the
+      // next tile's wait for its prefetched columns waits for nothing else)
+      if (__ballot(word != 0u) != 0ull) {
+        filled |= 1ull << ((cb - c0) >> 6);
+        if (cb != diag && word != 0u) atomicAdd(&colcnt[cb - c0 + lane], __popc(word));
+      }
     };
     float xn[D];
     if (PRUNE) {
@@ -273,6 +278,12 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
         for (int k = 0; k < D; ++k) xa[k] = col(k, na + lane);
         tile(cb + 64, xb);
       }
+    }
+    // the flags of the tiles from cs on, one per lane (a chunk has at most
+    // 64 column blocks); pruned-away tiles hold no bit
+    {
+      const int cbl = c0 + 64 * lane;
+      if (cbl >= cs && cbl < c1) flag[lane] = (uint8_t)((filled >> lane) & 1ull);
     }
     int mine = 0;
 #pragma unroll
