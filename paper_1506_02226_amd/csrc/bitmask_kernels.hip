@@ -449,12 +449,23 @@ __device__ __forceinline__ void for_flagged_words(const uint32_t *__restrict__ a
   }
 }
 
+// gate (caller's order): the passes run only when the core points' counts
+// sum to at least kHookDegree per point (st->core_degree, from the core
+// pass); below it the pair pass alone is cheaper.
+constexpr unsigned long long kHookDegree = 4;
+
+__device__ __forceinline__ bool hook_off(const DevState *gate, int n) {
+  return gate && __hip_atomic_load(&gate->core_degree, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) < kHookDegree * (unsigned long long)n;
+}
+
 __global__ __launch_bounds__(256) void k_merge_hook(const uint32_t *__restrict__ adj,
                                                     const uint8_t *__restrict__ tflag,
                                                     const uint32_t *__restrict__ corebits,
-                                                    int *__restrict__ parent, SweepScalars p) {
+                                                    int *__restrict__ parent, SweepScalars p,
+                                                    const DevState *gate) {
   const int rb = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
-  if (rb * 64 >= p.n) return;
+  if (rb * 64 >= p.n || hook_off(gate, p.n)) return;
   MergeRows m = merge_rows(tflag, corebits, rb, 0, p);
   m.q0 = max(0, m.q1 - 64);  // one batch of flags: the window below the diagonal
   bool seek = m.is_core;
@@ -471,9 +482,9 @@ __global__ __launch_bounds__(256) void k_merge_hook(const uint32_t *__restrict__
       [&]() { return __ballot(seek) != 0ull; });
 }
 
-__global__ void k_merge_compress(int *__restrict__ parent, int n) {
+__global__ void k_merge_compress(int *__restrict__ parent, int n, const DevState *gate) {
   const int i = blockIdx.x * 256 + (int)threadIdx.x;
-  if (i < n) {
+  if (i < n && !hook_off(gate, n)) {
     const int r = uf_find(parent, i);
     if (r != i) uf_store(parent + i, r);
   }
@@ -486,7 +497,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
                                                        int *__restrict__ parent,
                                                        int *__restrict__ jstar,
                                                        const int *__restrict__ okey,
-                                                       SweepScalars p) {
+                                                       SweepScalars p, const DevState *gate) {
   __shared__ int2 qbuf[4][128];
   const int lane = lane_id();
   const int w = wave_uniform(threadIdx.x >> 6);
@@ -495,11 +506,13 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
   if (rb * 64 >= p.n) return;
   const MergeRows m = merge_rows(tflag, corebits, rb, chunk, p);
   if (m.q0 >= m.q1) return;
+  // whether the hook and compress passes ran (their gate, read the same way)
+  const bool hooked = HOOKED && !hook_off(gate, p.n);
   const int i = m.i;
   bool seek = m.valid && !m.is_core;
   int best = kNoNeighbour;                                 // ORDERED, non-core rows
   const int my_key = (ORDERED && m.valid) ? okey[i] : i;  // key of row i in jstar
-  const int root_i = (HOOKED && m.is_core) ? parent[i] : -1;  // after the compress pass
+  const int root_i = (hooked && m.is_core) ? parent[i] : -1;  // after the compress pass
   WaveQueue qu{qbuf[w], 0, 64};
   for_flagged_words(
       adj, m, p.n_pad,
@@ -526,7 +539,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
         // core-core pairs
         uint32_t cc = m.is_core ? (word & cw) : 0u;
         if (__ballot(cc != 0u) == 0ull) return;
-        if (HOOKED) {
+        if (hooked) {
           const int pc = parent[q * 32 + (lane & 31)];  // lanes l and l + 32: column l
           const int P = __builtin_amdgcn_readlane(pc, __builtin_ctz(cw));
           if (__ballot(((cw >> (lane & 31)) & 1u) && pc != P) == 0ull) {
@@ -542,7 +555,7 @@ __global__ __launch_bounds__(256) void k_merge_bitmask(const uint32_t *__restric
           cc &= cc - 1u;
           // hooked, in the caller's order: a column whose parent is i's
           // root is in i's tree already (its parent is a common ancestor)
-          const bool join = (HOOKED && !ORDERED && has) ? parent[q * 32 + b] != root_i : has;
+          const bool join = (hooked && !ORDERED && has) ? parent[q * 32 + b] != root_i : has;
           wq_push(qu, join, i, q * 32 + b);
           wq_drain_union(qu, parent, false);
         }
@@ -602,8 +615,12 @@ hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) 
 // Without them every core-core pair there was a union, and the unions of a
 // cluster all contended for its few roots.  Measured per call (whole step):
 // blobs2d_small 0.096 -> 0.074 ms, the same recipe at n = 8,000 0.76 -> 0.43
-// ms, the blobs2d_200k recipe at n = 16,000 0.30 -> 0.18 ms.
-constexpr int kHookCallerOrderMax = 16384;
+// ms, the blobs2d_200k recipe at n = 16,000 0.30 -> 0.18 ms.  On sparse
+// inputs they cost more than they save (two launches and a scan: 6 to 11 us
+// more for step 3 where the core points' counts sum to at most 3 per point),
+// so in the caller's order they return at once below kHookDegree per point;
+// the pair pass is correct with or without them.  (kHookCallerOrderMax:
+// dbscan_internal.h.)
 
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s) {
   const int groups = (sc.n_pad / 64 + 3) / 4;
@@ -612,23 +629,25 @@ hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream
     SweepScalars whole = sc;  // the hook pass scans each row's words in one piece
     whole.nchunks = 1;
     whole.chunk = sc.n_pad / 32;
+    // in the caller's order the passes check the core points' degree first
+    const DevState *gate = b.okey ? nullptr : b.st;
     hipLaunchKernelGGL(k_merge_hook, dim3(groups), dim3(256), 0, s, (const uint32_t *)b.adjT,
-                       b.tflag, b.corebits, b.parent, whole);
+                       b.tflag, b.corebits, b.parent, whole, gate);
     hipLaunchKernelGGL(k_merge_compress, dim3((sc.n + 255) / 256), dim3(256), 0, s, b.parent,
-                       sc.n);
+                       sc.n, gate);
   }
   if (b.okey)
     hipLaunchKernelGGL((k_merge_bitmask<true, true>), dim3(groups * sc.nchunks), dim3(256), 0, s,
                        (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar, b.okey,
-                       sc);
+                       sc, nullptr);
   else if (hooked)
     hipLaunchKernelGGL((k_merge_bitmask<false, true>), dim3(groups * sc.nchunks), dim3(256), 0,
                        s, (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar,
-                       b.okey, sc);
+                       b.okey, sc, b.st);
   else
     hipLaunchKernelGGL((k_merge_bitmask<false, false>), dim3(groups * sc.nchunks), dim3(256), 0,
                        s, (const uint32_t *)b.adjT, b.tflag, b.corebits, b.parent, b.jstar,
-                       b.okey, sc);
+                       b.okey, sc, nullptr);
   return hipGetLastError();
 }
 

@@ -109,15 +109,17 @@ __device__ __forceinline__ void stage_body(const float *__restrict__ pts, int n,
 // ------------------------------------------------------------- core flags
 // corebits in the staged order; core[] (and, with a spatial order, the
 // counts) written in the caller's order.  With `count` the number of core
-// points goes to st->core_points (one atomic per block).  Every thread of the
-// block must call it (it synchronises the block).
+// points goes to st->core_points, and with `degree` the sum of the core
+// points' counts to st->core_degree (one atomic per block each).  Every
+// thread of the block must call it (it synchronises the block).
 __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n, int n_pad,
                                           int minpts, uint8_t *__restrict__ core,
                                           uint32_t *__restrict__ corebits, DevState *st, int bid,
                                           const int *__restrict__ perm = nullptr,
                                           int *__restrict__ counts_out = nullptr,
-                                          bool count = false) {
+                                          bool count = false, bool degree = false) {
   __shared__ unsigned block_cores;
+  __shared__ unsigned long long block_degree;
   const int i = bid * 256 + (int)threadIdx.x;
   const bool c = i < n && counts[i] >= minpts;
   if (i < n) {
@@ -135,12 +137,21 @@ __device__ __forceinline__ void core_body(const int *__restrict__ counts, int n,
     corebits[i >> 5] = (uint32_t)m;
     corebits[(i >> 5) + 1] = (uint32_t)(m >> 32);
   }
-  if (!count) return;  // uniform over the launch
-  if (threadIdx.x == 0) block_cores = 0u;
+  if (!count && !degree) return;  // uniform over the launch
+  if (threadIdx.x == 0) {
+    block_cores = 0u;
+    block_degree = 0ull;
+  }
   __syncthreads();
-  if (lane == 0 && m) atomicAdd(&block_cores, (unsigned)__popcll(m));
+  if (count && lane == 0 && m) atomicAdd(&block_cores, (unsigned)__popcll(m));
+  if (degree) {
+    unsigned long long v = c ? (unsigned long long)counts[i] : 0ull;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0 && v) atomicAdd(&block_degree, v);
+  }
   __syncthreads();
   if (threadIdx.x == 0 && block_cores) atomicAdd(&st->core_points, (unsigned long long)block_cores);
+  if (threadIdx.x == 0 && block_degree) atomicAdd(&st->core_degree, block_degree);
 }
 
 // --------------------------------------------- merge + border from the list

@@ -17,6 +17,7 @@ __global__ void k_reset_state(DevState *st, unsigned pair_segs) {
     st->noncore = 0;
     st->band_pairs = 0;
     st->core_points = 0;
+    st->core_degree = 0;
     st->edges = 0;
     st->band_list = 0;
     st->max_norm = 0;
@@ -45,9 +46,9 @@ __global__ void k_stage(const float *__restrict__ pts, int n, int d, int n_pad, 
 __global__ void k_core(const int *__restrict__ counts, int n, int n_pad, int minpts,
                        uint8_t *__restrict__ core, uint32_t *__restrict__ corebits,
                        DevState *st, const int *__restrict__ perm, int *__restrict__ counts_out,
-                       int count) {
+                       int count, int degree) {
   core_body(counts, n, n_pad, minpts, core, corebits, st, blockIdx.x, perm, counts_out,
-            count != 0);
+            count != 0, degree != 0);
 }
 
 // Non-core rows into a list (any order) for the border pass that repeats the
@@ -175,9 +176,9 @@ hipError_t run_stage(const float *pts, int n, int d, int n_pad, int d_pad, float
 
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
                     uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
-                    bool count, hipStream_t s) {
+                    bool count, hipStream_t s, bool degree) {
   hipLaunchKernelGGL(k_core, dim3((n_pad + 255) / 256), dim3(256), 0, s, counts, n, n_pad, minpts,
-                     core, corebits, st, ord.perm, counts_out, count ? 1 : 0);
+                     core, corebits, st, ord.perm, counts_out, count ? 1 : 0, degree ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -506,8 +506,11 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
   mark(1);
   // ---- step 2: core flags
   // the core-point total is a statistic: counted only when asked for
+  // the core points' degree gates the bitmask merge's hook passes in the
+  // caller's order (run_merge_bitmask)
   step(dbk::run_core(counts_k, ni, npad, minpts, core, corebits, st, ord, counts,
-                     stats != nullptr, s));
+                     stats != nullptr, s,
+                     bitmask && L.order != DBSCAN_ORDER_SPATIAL && npad <= dbk::kHookCallerOrderMax));
   mark(2);
   // ---- step 3: merge (union-find over core-core neighbour pairs) and border
   // points (lowest-index core neighbour)

@@ -36,7 +36,8 @@ struct DevState {
   unsigned long long band_list;    // pairs appended to the matrix-core band list
   unsigned long long max_norm;     // bit pattern of max |x_i| (float64, >= 0)
   float thr[2];                    // matrix-core filter thresholds (in, out)
-  unsigned long long reserved[2];
+  unsigned long long core_degree;   // sum of the core points' counts (when asked for)
+  unsigned long long reserved1;
   unsigned int box_lo[4], box_hi[4];  // bounding box of the input (order-preserving bits)
   unsigned long long tests;           // pair tests made by a pruned sweep
   // Pair list in segments (0 or 1: one list at `edges`): segment s holds

@@ -260,7 +260,7 @@ hipError_t run_border(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_core(const int *counts, int n, int n_pad, int minpts, uint8_t *core,
                     uint32_t *corebits, DevState *st, const Order &ord, int *counts_out,
-                    bool count, hipStream_t s);
+                    bool count, hipStream_t s, bool degree = false);
 hipError_t run_compact_noncore(const uint32_t *corebits, int n, int *list, DevState *st,
                                bool only_on_overflow, hipStream_t s);
 hipError_t run_merge_list(const Buffers &b, long long cap, hipStream_t s);
@@ -281,6 +281,10 @@ hipError_t run_mfma_count(const void *a_aug, const void *b_aug, const Buffers &b
                           const MfmaScalars &sc, int prec, hipStream_t s);
 hipError_t run_recheck_band(const float *pts, int d, const Buffers &b, double eps2,
                             long long band_cap, long long pair_cap, hipStream_t s);
+// Inputs of at most this many (padded) rows in the caller's order run the
+// bitmask merge's hook and compress passes, gated by the core points' degree
+// (run_merge_bitmask).
+constexpr int kHookCallerOrderMax = 16384;
 hipError_t run_merge_bitmask(const Buffers &b, const SweepScalars &sc, hipStream_t s);
 hipError_t run_labels(int n, const uint32_t *corebits, const int *jstar, int *parent, int *labels,
                       const DevState *st, const Order &ord, hipStream_t s);
