@@ -250,7 +250,9 @@ void dbscan_server::finish_locked(uint64_t id, int32_t state, int32_t err, int64
   Record &r = records[id];
   r.status.state = state;
   r.status.error = err;
-  r.status.t_done_ns = t_done;
+  // a loop job's completion is the device clock mapped to the host's, which
+  // is calibrated to within half a round trip: never before the admission
+  r.status.t_done_ns = t_done < r.status.t_admit_ns ? r.status.t_admit_ns : t_done;
   r.status.fallback = fallback;
   if (r.slot >= 0) {
     slot_job[r.slot] = 0;
@@ -594,13 +596,23 @@ int dbscan_server_create(int device, uint64_t hbm_budget_bytes, int32_t max_slot
   if (ok) {
     s->blocks = 3 * cus;
     s->ns_per_tick = 1e6 / (double)khz;
-    const int64_t a = now_ns();
-    ok = dbk::run_read_clock(s->d_clock, s->stream) == hipSuccess &&
-         hipMemcpyAsync(&s->dev0, s->d_clock, sizeof(long long), hipMemcpyDeviceToHost,
-                        s->stream) == hipSuccess &&
-         hipStreamSynchronize(s->stream) == hipSuccess;
-    const int64_t b = now_ns();
-    s->host0 = (a + b) / 2;
+    // the device clock read in the middle of a host interval: the shortest
+    // of four round trips (the first one also loads the kernel)
+    int64_t best = -1;
+    for (int k = 0; ok && k < 4; ++k) {
+      long long ticks = 0;
+      const int64_t a = now_ns();
+      ok = dbk::run_read_clock(s->d_clock, s->stream) == hipSuccess &&
+           hipMemcpyAsync(&ticks, s->d_clock, sizeof(long long), hipMemcpyDeviceToHost,
+                          s->stream) == hipSuccess &&
+           hipStreamSynchronize(s->stream) == hipSuccess;
+      const int64_t b = now_ns();
+      if (ok && (best < 0 || b - a < best)) {
+        best = b - a;
+        s->dev0 = ticks;
+        s->host0 = (a + b) / 2;
+      }
+    }
   }
   if (!ok) {
     (void)hipGetLastError();

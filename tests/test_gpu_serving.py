@@ -122,15 +122,24 @@ def test_served_jobs_arriving_while_others_run():
     (and the oracle).  When the small ones are admitted and which finishes
     first is up to the device's scheduling: the large job's kernels can hold
     every CU until they drain, and the loop's epoch boundaries wait for them
-    (the timings are printed)."""
+    (the timings are printed).  Every input and output is allocated before the
+    large job is submitted: an allocation in between may wait for the device,
+    and so for the large job."""
     # 200,000 points at d = 64 in float32 (no matrix cores, no pruning):
     # tens of milliseconds on a worker
     big = wl.mix64d_300k(0, n=200_000, eps_rule="q50")
     big_eps, big_minpts = big.eps, big.minpts
     small = _mixed_jobs(6, seed=12, n_max=2000)
+    xb = _gpu(big.points)
+    xs = [_gpu(p) for p, _, _ in small]
+    outs_dev = [(torch.empty(len(p), dtype=torch.int32, device="cuda:0"),
+                 torch.empty(len(p), dtype=torch.uint8, device="cuda:0"),
+                 torch.empty(len(p), dtype=torch.int32, device="cuda:0")) for p, _, _ in small]
+    torch.cuda.synchronize()
     with pkg.Server(max_slots=16) as srv:
-        jb = srv.submit(_gpu(big.points), big_eps, big_minpts, precision="fp32")
-        ids = [srv.submit(_gpu(p), eps, mp) for p, eps, mp in small]
+        jb = srv.submit(xb, big_eps, big_minpts, precision="fp32")
+        ids = [srv.submit(x, eps, mp, out=o)
+               for x, (_, eps, mp), o in zip(xs, small, outs_dev)]
         sts = [srv.wait(i, timeout=120) for i in ids]
         sb = srv.wait(jb, timeout=120)
         outs = [_host(srv.outputs(i)) for i in ids]
