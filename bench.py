@@ -451,8 +451,8 @@ def main(argv=None) -> int:
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); rows shard across GPUs only in the design notes.",
+        print(f"bench.py: the engine runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); sharding rows across GPUs is a design, not built.",
               file=sys.stderr)
         return 2
 
