@@ -335,3 +335,17 @@ def test_mfma_small_d_on_request(prec, d):
     pts = rng.uniform(0, 4, size=(900, d)).astype(np.float32)
     eps, minpts = 0.3 * np.sqrt(d), 4
     assert_same(run(pts, eps, minpts, precision=prec), orc.dbscan(pts, eps, minpts), f"d={d}")
+
+
+@pytest.mark.parametrize("n", [2000, 6000, 16000])
+@pytest.mark.parametrize("recipe", ["paper3d", "blobs2d_200k", "blobs2d_small"])
+def test_bitmask_merge_caller_order_hook_gate(recipe, n):
+    """In the caller's order, up to 16,384 rows, the bitmask merge runs its
+    hook and compress passes only when the core points' counts sum to at
+    least 4 per point, a decision taken on the device; the pair pass follows
+    it.  These recipes and sizes fall on both sides (paper3d at 2,000 has no
+    core point, blobs2d_small is dense): every output equals the oracle's."""
+    w = wl.by_name(recipe, 0, n)
+    gpu = run(w.points, w.eps, w.minpts, adjacency="bitmask", order="input", stats=True)
+    assert gpu[3]["adjacency_used"] == "bitmask" and gpu[3]["order_used"] == "input"
+    assert_same(gpu, c_oracle.dbscan(w.points, w.eps, w.minpts), f"{recipe} n={n}")
