@@ -205,7 +205,7 @@ int dbscan_fit_ex(const float *points, int64_t n, int32_t d, double eps, int32_t
  * process ends.  The default plan is used when its workspace fits; otherwise
  * the on-the-fly form runs with pair and band lists sized to the array (a
  * full pair list makes step 3 repeat the epsilon tests; results are the
- * same).  DBSCAN_E_NOMEM when even that does not fit: n above 890,112 at
+ * same).  DBSCAN_E_NOMEM when even that does not fit: n above 887,296 at
  * d = 3, 388,608 at d = 16, 120,320 at d = 64.  Every call on a GPU uses that
  * GPU's one array: calls that overlap on one GPU (different streams, or
  * different host threads without ordering) race and must be serialized by

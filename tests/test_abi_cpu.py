@@ -544,3 +544,26 @@ def test_struct_layouts_match_header(cname, pyname, tmp_path):
                                           text=True).stdout.split()]
     assert out[0] == ctypes.sizeof(cls)
     assert out[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_noalloc_limits_stated_in_the_header():
+    """dbscan_fit_noalloc falls back to the on-the-fly form with lists sized
+    to its array, and refuses (n, d) whose fixed part (that plan with lists
+    of one entry) plus 1 KiB of rounding slack exceeds the array.  The
+    limits include/dbscan.h states are exactly where that happens: the
+    stated n fits and one more row does not (a workspace section that grows
+    moves them)."""
+    L = _lib.load()
+    room = 64 << 20  # DBSCAN_NOALLOC_SCRATCH_BYTES
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "dbscan.h")).read()
+    assert "#define DBSCAN_NOALLOC_SCRATCH_BYTES (64ull << 20)" in hdr
+    out = ctypes.c_uint64()
+
+    def fixed(n, d):
+        o = _lib.make_opts("onthefly", pair_capacity=1, band_capacity=1)
+        assert L.dbscan_workspace_size(n, d, ctypes.byref(o), ctypes.byref(out)) == 0
+        return out.value
+
+    for n, d in ((887_296, 3), (388_608, 16), (120_320, 64)):
+        assert f"{n:,}" in hdr, n
+        assert fixed(n, d) + 1024 <= room < fixed(n + 1, d) + 1024, (n, d)

@@ -60,7 +60,7 @@ def test_noalloc_equals_fit_ex_twice(first, second):
 def test_noalloc_rejects_sizes_beyond_the_array():
     L = _lib.load()
     # rejected on the host before any device work: the pointers are never read
-    for n, d in ((890_113, 3), (388_609, 16), (120_321, 64)):
+    for n, d in ((887_297, 3), (388_609, 16), (120_321, 64)):
         rc = L.dbscan_fit_noalloc(0x1000, n, d, 1.0, 5, 0x2000, 0x3000, 0x4000, None)
         assert rc == _lib.DBSCAN_E_NOMEM, (n, d, rc)
     rc = L.dbscan_fit_noalloc(None, 10, 2, 1.0, 5, 0x2000, 0x3000, 0x4000, None)
