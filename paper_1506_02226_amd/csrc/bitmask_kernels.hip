@@ -114,13 +114,19 @@ __device__ __forceinline__ void bitmask_body(const float *__restrict__ soa,
     const int diag = row0 & ~63;
     const int cs = max(c0, diag);
     if (cs >= c1) continue;  // wave-uniform
-    // the rows: coordinates (direct form) or -2 fl(x - c) (HOIST)
+    // the rows: coordinates (direct form) or -2 fl(x - c) (HOIST).  One
+    // coalesced load per coordinate (lane l holds row row0 + l % 32), then
+    // each row's value broadcast from its lane: loaded one by one, the
+    // values went through the same few registers, one round trip each
     float xr[R][D];
     const float *rows = HOIST ? hv.a : soa;
 #pragma unroll
-    for (int r = 0; r < R; ++r)
+    for (int k = 0; k < D; ++k) {
+      const int v = __builtin_bit_cast(int, rows[(size_t)k * sc.n_pad + row0 + (lane & (R - 1))]);
 #pragma unroll
-      for (int k = 0; k < D; ++k) xr[r][k] = to_vgpr(rows[(size_t)k * sc.n_pad + row0 + r]);
+      for (int r = 0; r < R; ++r)
+        xr[r][k] = to_vgpr(__builtin_bit_cast(float, __builtin_amdgcn_readlane(v, r)));
+    }
     float cen[2][D];     // HOIST: the origins of the two 16-row halves
     float gate[R / G];   // largest "out" threshold of each group
 #pragma unroll
