@@ -105,16 +105,19 @@ class HipEvents:
             self.lib.hipEventDestroy(e)
 
 
-def measured_traffic(kernel: str, workload: str):
+def measured_traffic(kernel: str, workload: str, form: dict):
     """HBM bytes per launch of `kernel` on `workload` from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source
-    (else None)."""
+    rocprofv3 counter summary, if it was taken in the same form (adjacency,
+    precision, row order, pruning: a pruned launch runs another kernel) and
+    on the current kernel source (else None)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if rec.get("form") != form:
+        return None
     for rel, want in rec["sources_sha256"].items():
         src = os.path.join(ROOT, rel)
         if not os.path.exists(src):
@@ -569,7 +572,9 @@ def main(argv=None) -> int:
         "roofline": roof,
     }
     rec["tests_per_step"] = int(tests)
-    roof["traffic"] = measured_traffic(roof["kernel"], w.name)
+    roof["traffic"] = measured_traffic(roof["kernel"], w.name, {
+        "adjacency": st["adjacency_used"], "precision": st["precision_used"],
+        "order": st["order_used"], "prune": bool(st["pruned"])})
 
     if args.transfer_steps > 0:
         # Table V's "with data transmission" column: pageable host points in,
